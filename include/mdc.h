@@ -1,0 +1,191 @@
+/*
+ * mdc.h -- C ABI of the MI355X (gfx950) multi-dimensional convolution library.
+ *
+ * The operator (Theory section, Eq.2-4) maps a real input x[t][r][v]
+ * (nt x nr x nv, time outermost) to y[t][s][v] (nt x ns x nv):
+ *
+ *   forward  y = F^H I^H K I F x      (Eq.3, left)
+ *   adjoint  x = F^H I^H K^H I F y    (Eq.3, right)
+ *
+ * F is the orthogonal real FFT along t (scaled by nt^-1/2 both ways,
+ * positive frequencies only), I keeps the first nfmax bins and its adjoint
+ * zero-pads, and K is block diagonal with one dense complex slice K_f
+ * (ns x nr) per retained frequency (Eq.4), already multiplied by the
+ * integration weight dx_R.  The inverse transform takes the real parts of
+ * the DC and Nyquist bins, so the adjoint is exact: no time reversal is
+ * applied besides the conjugate transpose of each slice.
+ *
+ * Memory: the library never allocates device memory.  The caller obtains
+ * sizes from mdc_query_sizes / lsqr_query_sizes / serve_query_sizes and
+ * passes device buffers it owns (e.g. from PyTorch); the library never frees
+ * them.  Host-side handles (mdc_op, mdc_server) are owned by the library
+ * and released by the matching *_destroy call.
+ *
+ * Streams: every `stream` argument is a hipStream_t passed as void* (NULL is
+ * the default stream).  Calls only enqueue work and return; results are
+ * ready when the stream reaches that point.  One mdc_op owns one workspace,
+ * so applies on the same op must be issued in order on one stream; distinct
+ * ops (each with its own workspace) may run concurrently.
+ *
+ * Errors: every function returns an mdc_status; nothing throws.  On error
+ * no work has been enqueued (argument checks run first) except for
+ * MDC_EDEVICE, which reports a failed launch.  mdc_last_error() returns a
+ * thread-local description of the last failure.
+ *
+ * Layouts (row-major, last index fastest):
+ *   time vectors   float   [nt][n][nv]
+ *   kernel input   float2  [nfmax][ns][nr]   (complex64: re, im)
+ *   onsets         int32   [n][nv]           (window half-width in samples)
+ */
+#ifndef MDC_H
+#define MDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MDC_OK = 0,
+  MDC_EINVAL = -1,     /* bad argument: null/misaligned pointer, size out of range */
+  MDC_ENOMEM = -2,     /* a buffer is too small, or a request can never fit its budget */
+  MDC_EDEVICE = -3,    /* a HIP launch or runtime call failed */
+  MDC_EBUSY = -4,      /* the object is in use (server still has requests) */
+  MDC_ENOTREADY = -5,  /* a served request has not finished yet */
+  MDC_ECANCELED = -6,  /* a served request was cancelled or failed */
+  MDC_ENOTSUP = -7     /* a valid but unsupported combination (e.g. nt not a power of 2) */
+} mdc_status;
+
+/* Storage format of the resident kernel.  Products always accumulate in FP32.
+ *   MDC_FP32   complex64, 8 bytes per element.
+ *   MDC_FP16S  FP16 pairs scaled by a power of two per frequency slice (4 bytes).
+ *   MDC_BF16   BF16 pairs (4 bytes).
+ *   MDC_BF16X2 BF16 hi + lo pairs, hi = RNE(k), lo = RNE(k - hi) (8 bytes).  */
+typedef enum { MDC_FP32 = 0, MDC_FP16S = 1, MDC_BF16 = 2, MDC_BF16X2 = 3 } mdc_prec;
+
+typedef struct mdc_op mdc_op;
+
+typedef struct {
+  int nt;        /* time samples; a power of two in [16, 2048] */
+  int nfmax;     /* retained bins, 1 <= nfmax <= nt/2 + 1 (Eq.2, omega_max) */
+  int ns;        /* rows of each slice: output traces x_B */
+  int nr;        /* columns of each slice: integration traces x_R */
+  int max_cols;  /* widest column count (virtual points, fused blocks) per apply, >= 1 */
+  mdc_prec prec; /* resident storage format */
+} mdc_desc;
+
+/* Thread-local text of the last error (never NULL). */
+const char* mdc_last_error(void);
+
+/* Bytes of the resident buffer (kernel + tables, 256-byte aligned pieces) and
+ * of the per-apply workspace (spectra of max_cols columns). */
+mdc_status mdc_query_sizes(const mdc_desc* desc, size_t* resident_bytes, size_t* workspace_bytes);
+
+/* Create an operator over caller-owned device buffers `resident` and `workspace`
+ * (256-byte aligned, at least the queried sizes).  Writes the FFT tables into
+ * `resident` on `stream`.  The kernel itself is loaded by mdc_set_kernel or
+ * mdc_synth_kernel before the first apply. */
+mdc_status mdc_create(const mdc_desc* desc, void* resident, void* workspace, void* stream,
+                      mdc_op** out);
+
+/* Load the kernel (Eq.4 slices, integration weight included) from a device array
+ * K [nfmax][ns][nr] complex64, multiplying element (f, s, r) by
+ * scale * (col_weight ? col_weight[r] : 1) (Theory section: constant or
+ * receiver-dependent dx_R pre-multiplied into the columns), and converting it to
+ * the storage format.  col_weight is a device array of nr floats or NULL.
+ * K may be released once the stream passes this call. */
+mdc_status mdc_set_kernel(mdc_op* op, const void* K, double scale, const float* col_weight,
+                          void* stream);
+
+/* Synthetic hyperbolic-event reflection kernel generated on the device in FP64
+ * and rounded once to the storage format (a stand-in for the paper's
+ * finite-difference data; see the header comment of the generator):
+ *   K[f,s,r] = kappa dA W(f/(nt dt)) sum_k a_k exp(-2 pi i f tau_k(s,r)/(nt dt))
+ *              + noise sigma_f (n1 + i n2)/sqrt(2)
+ * on a square grid of nx*nx traces with spacing dx; rows and columns are the
+ * full-grid trace indices s_index[i], r_index[j] (device int32 arrays of ns and
+ * nr entries, or NULL for the identity).  The noise normals come from the
+ * SplitMix64 counter generator keyed by (seed, stream 4, counter 2q, 2q+1),
+ * q = (f * nx^2 + s) * nx^2 + r. */
+typedef struct {
+  int nx;              /* grid side; full grid has nx*nx traces */
+  double dt, dx;       /* sampling (s, m) */
+  double fp;           /* Ricker peak frequency of the kernel spectrum (Hz) */
+  double kappa;        /* overall scale */
+  double noise;        /* relative noise level */
+  double area;         /* dA: areal element multiplied in (m^2) */
+  uint64_t seed;
+  int nev;             /* number of events (<= 64) */
+  const double* amp;   /* host arrays of nev entries: amplitudes, */
+  const double* t0;    /*   zero-offset times (s), */
+  const double* vel;   /*   moveout velocities (m/s) */
+  const int* s_index;  /* device, ns entries or NULL */
+  const int* r_index;  /* device, nr entries or NULL */
+} mdc_synth_desc;
+mdc_status mdc_synth_kernel(mdc_op* op, const mdc_synth_desc* sd, void* stream);
+
+/* Read back element (f, s, r) of the resident kernel as complex64 (host
+ * pointers re/im; synchronises the stream).  For tests of the loaders. */
+mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, float* re, float* im);
+
+/* Forward (Eq.3 left): y[t][s][v] from x[t][r][v], 1 <= nv <= max_cols.
+ * x and y are device float arrays and must not overlap. */
+mdc_status mdc_forward(mdc_op* op, const float* x, float* y, int nv, void* stream);
+
+/* Adjoint (Eq.3 right): x[t][r][v] from y[t][s][v]. */
+mdc_status mdc_adjoint(mdc_op* op, const float* y, float* x, int nv, void* stream);
+
+/* Marchenko operator of Eq.5 on a square op (ns == nr == n) with 2*nv <= max_cols:
+ *   forward  (o0, o1) = (in0 - Theta R in1,  in1 - Theta R* in0)
+ *   adjoint  (o0, o1) = (in0 - R*^H Theta in1,  in1 - R^H Theta in0)
+ * R uses the kernel, R* its complex conjugate (no transpose).  Theta[t][s][v] = 1
+ * when |lag(t)| < onset[s][v], lag(t) = t for t < nt/2 and t - nt otherwise.
+ * One pass over the kernel serves both blocks (columns [R-input | conj R*-input]).
+ * All arrays are device arrays [nt][n][nv]; outputs must not alias inputs. */
+mdc_status mch_forward(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1,
+                       float* out0, float* out1, void* stream);
+mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1,
+                       float* out0, float* out1, void* stream);
+
+/* Per-stage timing with HIP events on the apply stream (for measurement).
+ * enable != 0 starts recording; mdc_profile_read synchronises and returns the
+ * summed milliseconds and launch counts of each stage since the last read:
+ * [0] forward FFT, [1] kernel product (forward form), [2] kernel product
+ * (adjoint form), [3] inverse FFT. */
+mdc_status mdc_profile(mdc_op* op, int enable);
+mdc_status mdc_profile_read(mdc_op* op, double ms[4], int counts[4]);
+
+mdc_status mdc_destroy(mdc_op* op);
+
+/* ----------------------------------------------------------------- LSQR ----
+ * LSQR (Paige & Saunders 1982; damping 0, x0 = 0, fixed niter) on the MDC
+ * operator (kind MDC_OP_MDC: A = C, model [nt][nr][nv], data [nt][ns][nv]) or
+ * on the Marchenko operator (kind MDC_OP_MARCHENKO: A = M, model and data two
+ * blocks [2][nt][n][nv]).  Vectors are FP32 on the device; alpha, beta, rho,
+ * rhobar, c, s, theta, phi, phibar and the norms are FP64 on the device.  The
+ * host does not synchronise inside the solve.  The paper runs CGLS for 10
+ * iterations (Applications section); LSQR produces the same iterates in exact
+ * arithmetic. */
+typedef enum { MDC_OP_MDC = 0, MDC_OP_MARCHENKO = 1 } mdc_opkind;
+typedef struct {
+  mdc_opkind kind;
+  int nv;             /* virtual points */
+  int niter;          /* iterations (>= 0) */
+  const int* onset;   /* Marchenko window onsets [n][nv] (device), else NULL */
+} lsqr_desc;
+
+/* Bytes of the workspace lsqr_solve needs for this descriptor. */
+mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_bytes);
+
+/* b: data (device, float); x: model output (device, float, overwritten);
+ * hist: device double array of niter+1 entries receiving phibar (the residual
+ * norm estimate) after each iteration, or NULL; work: device workspace. */
+mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist,
+                      void* work, size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDC_H */

@@ -1,0 +1,425 @@
+// C ABI of the MDC library: argument checks, buffer carving and the order of
+// launches of each apply (Eq.3 chain: truncated real FFT, per-frequency
+// product, zero-padded inverse FFT with fused epilogue).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "store.hpp"
+
+struct mdc_op {
+  mdc_desc d;
+  char* resident;
+  char* work;
+  float2* tw;        // [nt] exp(-2 pi i k / nt)
+  float* fscale;     // [nfmax] per-frequency storage scale (FP16S), else unused
+  void* kstore;      // stored kernel
+  float2* specR;     // [nfmax][nr][max_cols]
+  float2* specS;     // [nfmax][ns][max_cols]
+  bool kernel_ready;
+  std::vector<float2> tw_host;
+  // profiling
+  bool prof;
+  struct Ev { int stage; hipEvent_t a, b; };
+  std::vector<Ev> evs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace mdc {
+
+static thread_local char g_err[512] = "no error";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+mdc_status fail(mdc_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+mdc_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MDC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return MDC_OK;
+}
+
+size_t store_bytes(const mdc_desc& d) {
+  const size_t elems = (size_t)d.nfmax * d.ns * kernel_ld(d.nr);
+  switch (d.prec) {
+    case MDC_FP32: return elems * 8;
+    case MDC_FP16S: return elems * 4;
+    case MDC_BF16: return elems * 4;
+    case MDC_BF16X2: return elems * 8;
+  }
+  return 0;
+}
+
+mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* /*kscale*/, int adjoint,
+                          const float2* in, float2* out, int ncols, hipStream_t st) {
+  if (d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported by the product", (int)d.prec);
+  return gemv_launch(d, static_cast<const float2*>(kstore), kernel_ld(d.nr), adjoint, in, out, ncols, st);
+}
+
+}  // namespace mdc
+
+using namespace mdc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+mdc_status check_desc(const mdc_desc* d) {
+  if (!d) return fail(MDC_EINVAL, "descriptor is NULL");
+  if (d->nt < 16 || d->nt > 2048 || (d->nt & (d->nt - 1)) != 0)
+    return fail(MDC_ENOTSUP, "nt=%d: must be a power of two in [16, 2048]", d->nt);
+  if (d->nfmax < 1 || d->nfmax > d->nt / 2 + 1) return fail(MDC_EINVAL, "nfmax=%d outside [1, nt/2+1]", d->nfmax);
+  if (d->ns < 1 || d->nr < 1) return fail(MDC_EINVAL, "ns=%d, nr=%d must be positive", d->ns, d->nr);
+  if (d->max_cols < 1 || d->max_cols > 4096) return fail(MDC_EINVAL, "max_cols=%d outside [1, 4096]", d->max_cols);
+  if (d->prec < MDC_FP32 || d->prec > MDC_BF16X2) return fail(MDC_EINVAL, "unknown storage format %d", (int)d->prec);
+  return MDC_OK;
+}
+
+struct Layout {
+  size_t tw, fscale, kstore, resident;
+  size_t specR, specS, work;
+};
+
+Layout layout_of(const mdc_desc& d) {
+  Layout L{};
+  size_t off = 0;
+  L.tw = off; off = align_up(off + (size_t)d.nt * 8, kAlign);
+  L.fscale = off; off = align_up(off + (size_t)d.nfmax * 4, kAlign);
+  L.kstore = off; off = align_up(off + store_bytes(d), kAlign);
+  L.resident = off;
+  off = 0;
+  L.specR = off; off = align_up(off + (size_t)d.nfmax * d.nr * d.max_cols * 8, kAlign);
+  L.specS = off; off = align_up(off + (size_t)d.nfmax * d.ns * d.max_cols * 8, kAlign);
+  L.work = off;
+  return L;
+}
+
+hipEvent_t take_event(mdc_op* op) {
+  if (!op->pool.empty()) {
+    hipEvent_t e = op->pool.back();
+    op->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Scoped stage timer: records an event pair around the launches of one stage.
+struct Stage {
+  mdc_op* op;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Stage(mdc_op* o, int s, hipStream_t stream) : op(o), stage(s), st(stream) {
+    if (op->prof) {
+      a = take_event(op);
+      if (a) hipEventRecord(a, st);
+    }
+  }
+  ~Stage() {
+    if (op->prof && a) {
+      hipEvent_t b = take_event(op);
+      if (b) {
+        hipEventRecord(b, st);
+        op->evs.push_back({stage, a, b});
+      }
+    }
+  }
+};
+
+mdc_status check_vec(const void* p, const char* name) {
+  if (!p) return fail(MDC_EINVAL, "%s is NULL", name);
+  if (!aligned(p, 4)) return fail(MDC_EINVAL, "%s is not 4-byte aligned", name);
+  return MDC_OK;
+}
+
+mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st) {
+  const mdc_desc& d = op->d;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
+  if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
+  mdc_status s;
+  if ((s = check_vec(in, "input")) != MDC_OK) return s;
+  if ((s = check_vec(out, "output")) != MDC_OK) return s;
+  const int nin = adjoint ? d.ns : d.nr;
+  const int nout = adjoint ? d.nr : d.ns;
+  float2* spec_in = adjoint ? op->specS : op->specR;
+  float2* spec_out = adjoint ? op->specR : op->specS;
+  {
+    Stage t(op, 0, st);
+    FftSeg seg{in, nullptr, 0, 0};
+    if ((s = rfft_launch(op->tw, d.nt, d.nfmax, nin, nv, nv, seg, spec_in, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, adjoint ? 2 : 1, st);
+    if ((s = product_launch(d, op->kstore, op->fscale, adjoint, spec_in, spec_out, nv, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, 3, st);
+    IfftSeg seg{out, nullptr, nullptr, 0, 0, 1.0f};
+    if ((s = irfft_launch(op->tw, d.nt, d.nfmax, nout, nv, nv, seg, spec_out, st)) != MDC_OK) return s;
+  }
+  return MDC_OK;
+}
+
+// Marchenko block operator (Eq.5): one kernel pass with columns [block for R | conj block for R*].
+mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
+                           float* out1, int adjoint, hipStream_t st) {
+  const mdc_desc& d = op->d;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
+  if (nv < 1 || 2 * nv > d.max_cols) return fail(MDC_EINVAL, "2*nv=%d outside [2, max_cols=%d]", 2 * nv, d.max_cols);
+  mdc_status s;
+  if ((s = check_vec(onset, "onset")) != MDC_OK) return s;
+  if ((s = check_vec(in0, "in0")) != MDC_OK) return s;
+  if ((s = check_vec(in1, "in1")) != MDC_OK) return s;
+  if ((s = check_vec(out0, "out0")) != MDC_OK) return s;
+  if ((s = check_vec(out1, "out1")) != MDC_OK) return s;
+  const int n = d.ns, N = 2 * nv;
+  float2* spec_in = adjoint ? op->specS : op->specR;
+  float2* spec_out = adjoint ? op->specR : op->specS;
+  {
+    Stage t(op, 0, st);
+    // forward: R acts on in1, R* on in0; adjoint: R^H on Theta in0, R*^H on Theta in1
+    const int* pre = adjoint ? onset : nullptr;
+    FftSeg a{adjoint ? in0 : in1, pre, 0, 0};
+    FftSeg b{adjoint ? in1 : in0, pre, 1, nv};
+    if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_in, st)) != MDC_OK) return s;
+    if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_in, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, adjoint ? 2 : 1, st);
+    if ((s = product_launch(d, op->kstore, op->fscale, adjoint, spec_in, spec_out, N, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, 3, st);
+    const int* post = adjoint ? nullptr : onset;
+    // forward: out0 = in0 - Theta R in1 (cols 0..nv), out1 = in1 - Theta R* in0 (cols nv..2nv, conj)
+    // adjoint: out1 = in1 - R^H Theta in0 (cols 0..nv), out0 = in0 - R*^H Theta in1 (cols nv..2nv, conj)
+    IfftSeg a{adjoint ? out1 : out0, adjoint ? in1 : in0, post, 0, 0, -1.0f};
+    IfftSeg b{adjoint ? out0 : out1, adjoint ? in0 : in1, post, 1, nv, -1.0f};
+    if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_out, st)) != MDC_OK) return s;
+    if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_out, st)) != MDC_OK) return s;
+  }
+  return MDC_OK;
+}
+
+// Element-wise scaled conversion of a complex64 kernel into the resident store.
+// Element-wise scaled conversion of a complex64 kernel [nfmax*ns][nr] into the
+// resident store [nfmax*ns][ldk] (pad columns zero).
+__global__ void load_kernel_f32(const float2* __restrict__ K, float2* __restrict__ out, size_t count, int nr,
+                                int ldk, double scale, const float* __restrict__ w) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = i / (size_t)ldk;
+    const int r = (int)(i - row * (size_t)ldk);
+    float2 v = make_float2(0.f, 0.f);
+    if (r < nr) {
+      const double m = scale * (w ? (double)w[r] : 1.0);
+      const float2 k = K[row * nr + r];
+      v = make_float2((float)(k.x * m), (float)(k.y * m));
+    }
+    out[i] = v;
+  }
+}
+
+}  // namespace
+
+namespace mdc {
+mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld);
+size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld);
+mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
+                    void* work, hipStream_t st);
+
+// One application of the solver's operator (MDC or Marchenko); Marchenko vectors are two
+// contiguous blocks of `half` elements.
+mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
+                    size_t half, hipStream_t st) {
+  if (kind == MDC_OP_MARCHENKO)
+    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st);
+  return apply_plain(op, in, out, nv, adjoint, st);
+}
+}  // namespace mdc
+
+extern "C" {
+
+const char* mdc_last_error(void) { return g_err; }
+
+mdc_status mdc_query_sizes(const mdc_desc* desc, size_t* resident_bytes, size_t* workspace_bytes) {
+  mdc_status s = check_desc(desc);
+  if (s != MDC_OK) return s;
+  const Layout L = layout_of(*desc);
+  if (resident_bytes) *resident_bytes = L.resident;
+  if (workspace_bytes) *workspace_bytes = L.work;
+  return MDC_OK;
+}
+
+mdc_status mdc_create(const mdc_desc* desc, void* resident, void* workspace, void* stream, mdc_op** out) {
+  mdc_status s = check_desc(desc);
+  if (s != MDC_OK) return s;
+  if (!out) return fail(MDC_EINVAL, "out is NULL");
+  if (!resident || !aligned(resident, kAlign)) return fail(MDC_EINVAL, "resident must be non-NULL and 256-byte aligned");
+  if (!workspace || !aligned(workspace, kAlign)) return fail(MDC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  const Layout L = layout_of(*desc);
+  mdc_op* op = new (std::nothrow) mdc_op();
+  if (!op) return fail(MDC_ENOMEM, "host allocation failed");
+  op->d = *desc;
+  op->resident = static_cast<char*>(resident);
+  op->work = static_cast<char*>(workspace);
+  op->tw = reinterpret_cast<float2*>(op->resident + L.tw);
+  op->fscale = reinterpret_cast<float*>(op->resident + L.fscale);
+  op->kstore = op->resident + L.kstore;
+  op->specR = reinterpret_cast<float2*>(op->work + L.specR);
+  op->specS = reinterpret_cast<float2*>(op->work + L.specS);
+  op->kernel_ready = false;
+  op->prof = false;
+  // FFT table in FP64, rounded once: tw[k] = exp(-2 pi i k / nt)
+  op->tw_host.resize(desc->nt);
+  for (int k = 0; k < desc->nt; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)desc->nt;
+    op->tw_host[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(op->tw, op->tw_host.data(), (size_t)desc->nt * sizeof(float2), hipMemcpyHostToDevice, st) !=
+      hipSuccess) {
+    delete op;
+    return fail(MDC_EDEVICE, "uploading FFT table failed");
+  }
+  *out = op;
+  return MDC_OK;
+}
+
+mdc_status mdc_set_kernel(mdc_op* op, const void* K, double scale, const float* col_weight, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  if (!K || !aligned(K, 8)) return fail(MDC_EINVAL, "K must be non-NULL and 8-byte aligned");
+  if (op->d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported yet", (int)op->d.prec);
+  const int ldk = kernel_ld(op->d.nr);
+  const size_t count = (size_t)op->d.nfmax * op->d.ns * ldk;
+  hipLaunchKernelGGL(load_kernel_f32, dim3(4096), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const float2*>(K), static_cast<float2*>(op->kstore), count, op->d.nr, ldk, scale,
+                     col_weight);
+  mdc_status s = check_launch("load_kernel_f32");
+  if (s == MDC_OK) op->kernel_ready = true;
+  return s;
+}
+
+mdc_status mdc_synth_kernel(mdc_op* op, const mdc_synth_desc* sd, void* stream) {
+  if (!op || !sd) return fail(MDC_EINVAL, "op or descriptor is NULL");
+  StoreRef ref{op->kstore, op->fscale, op->d.nfmax, op->d.ns, op->d.nr, kernel_ld(op->d.nr)};
+  mdc_status s = synth_launch(op->d, *sd, ref, static_cast<hipStream_t>(stream));
+  if (s == MDC_OK) op->kernel_ready = true;
+  return s;
+}
+
+mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, float* re, float* im) {
+  if (!op || !re || !im) return fail(MDC_EINVAL, "NULL argument");
+  const mdc_desc& d = op->d;
+  if (f < 0 || f >= d.nfmax || s < 0 || s >= d.ns || r < 0 || r >= d.nr) return fail(MDC_EINVAL, "index out of range");
+  if (d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported yet", (int)d.prec);
+  float2 v;
+  const float2* p = static_cast<const float2*>(op->kstore) + ((size_t)f * d.ns + s) * kernel_ld(d.nr) + r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(&v, p, sizeof v, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return fail(MDC_EDEVICE, "reading kernel element failed");
+  *re = v.x;
+  *im = v.y;
+  return MDC_OK;
+}
+
+mdc_status mdc_forward(mdc_op* op, const float* x, float* y, int nv, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_plain(op, x, y, nv, 0, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mdc_adjoint(mdc_op* op, const float* y, float* x, int nv, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_plain(op, y, x, nv, 1, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mch_forward(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
+                       float* out1, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_marchenko(op, onset, nv, in0, in1, out0, out1, 0, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
+                       float* out1, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_marchenko(op, onset, nv, in0, in1, out0, out1, 1, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mdc_profile(mdc_op* op, int enable) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  op->prof = enable != 0;
+  return MDC_OK;
+}
+
+mdc_status mdc_profile_read(mdc_op* op, double ms[4], int counts[4]) {
+  if (!op || !ms || !counts) return fail(MDC_EINVAL, "NULL argument");
+  for (int i = 0; i < 4; ++i) { ms[i] = 0.0; counts[i] = 0; }
+  mdc_status st = MDC_OK;
+  for (auto& e : op->evs) {
+    float t = 0.f;
+    if (hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) {
+      st = fail(MDC_EDEVICE, "reading profile events failed");
+    } else {
+      ms[e.stage] += t;
+      counts[e.stage] += 1;
+    }
+    op->pool.push_back(e.a);
+    op->pool.push_back(e.b);
+  }
+  op->evs.clear();
+  return st;
+}
+
+mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_bytes) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  mdc_status s = lsqr_check(op, op->d, ld);
+  if (s != MDC_OK) return s;
+  if (!work_bytes) return fail(MDC_EINVAL, "work_bytes is NULL");
+  *work_bytes = lsqr_work_bytes(op->d, *ld);
+  return MDC_OK;
+}
+
+mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist, void* work,
+                      size_t work_bytes, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  mdc_status s = lsqr_check(op, op->d, ld);
+  if (s != MDC_OK) return s;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if ((s = check_vec(b, "b")) != MDC_OK) return s;
+  if ((s = check_vec(x, "x")) != MDC_OK) return s;
+  if (!work || !aligned(work, 256)) return fail(MDC_EINVAL, "work must be non-NULL and 256-byte aligned");
+  if (work_bytes < lsqr_work_bytes(op->d, *ld))
+    return fail(MDC_ENOMEM, "work has %zu bytes, %zu needed", work_bytes, lsqr_work_bytes(op->d, *ld));
+  if (hist && !aligned(hist, 8)) return fail(MDC_EINVAL, "hist must be 8-byte aligned");
+  return lsqr_run(op, op->d, *ld, b, x, hist, work, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mdc_destroy(mdc_op* op) {
+  if (!op) return MDC_OK;
+  for (auto& e : op->evs) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  for (auto e : op->pool) hipEventDestroy(e);
+  delete op;
+  return MDC_OK;
+}
+
+}  // extern "C"

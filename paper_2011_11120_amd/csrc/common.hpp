@@ -1,0 +1,65 @@
+// Shared device/host helpers of the HIP library (not used by the oracle).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/mdc.h"
+
+namespace mdc {
+
+// ------------------------------------------------------------ status -------
+void set_error(const char* fmt, ...);
+mdc_status fail(mdc_status st, const char* fmt, ...);
+mdc_status check_launch(const char* what);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// ----------------------------------------------------- complex helpers -----
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ---------------------------------------------------- window (Theta) -------
+// Theta[t][s][v] = 1 when |lag(t)| < onset, lag(t) = t (t < nt/2) else t - nt.
+__device__ __forceinline__ bool in_window(int t, int nt, int onset) {
+  int lag = (2 * t < nt) ? t : nt - t;
+  return lag < onset;
+}
+
+// --------------------------------------------------------- launchers -------
+// Spectra are complex64 [nfmax][n][ldc]; a segment is a run of nv columns
+// starting at column c0, fed from/to a time-domain array [nt][n][nv].
+struct FftSeg {
+  const float* in;     // time-domain input [nt][n][nv]
+  const int* onset;    // optional pre-window [n][nv] (adjoint Marchenko), or nullptr
+  int conj;            // conjugate the spectrum
+  int c0;              // first spectral column
+};
+struct IfftSeg {
+  float* out;          // time-domain output [nt][n][nv]
+  const float* ident;  // optional identity term added: out = ident + sign * Theta * y
+  const int* onset;    // optional post-window [n][nv], or nullptr
+  int conj;            // conjugate the spectrum before the inverse
+  int c0;              // first spectral column
+  float sign;          // multiplier of the transformed term
+};
+
+// FFT tables in the resident buffer: tw[k] = exp(-2 pi i k / nt), k < nt.
+mdc_status rfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int ldc, const FftSeg& seg,
+                       float2* spec, hipStream_t st);
+mdc_status irfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int ldc, const IfftSeg& seg,
+                        const float2* spec, hipStream_t st);
+
+// Kernel product over all frequencies: forward Y_f = K_f X_f (ns x nr times nr x ncols),
+// adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].
+mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* kscale, int adjoint,
+                          const float2* in, float2* out, int ncols, hipStream_t st);
+
+}  // namespace mdc

@@ -1,0 +1,225 @@
+// LSQR on the device (Paige & Saunders, ACM TOMS 8(1) 1982; damping 0, x0 = 0,
+// fixed iteration count).  The paper solves the Marchenko equations (Eq.5)
+// and the MDD equations (Eq.8) with a gradient solver (CGLS, 10 iterations);
+// LSQR yields the same iterates in exact arithmetic.
+//
+// Vectors are FP32; every scalar of the recurrence (alpha, beta, rho, rhobar,
+// c, s, theta, phi, phibar) and every norm is FP64 and lives on the device,
+// so the host enqueues the whole solve without synchronising.  Norms are
+// reduced in two fixed-shape stages (per-block FP64 partials, then one block),
+// so results do not depend on scheduling.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace mdc {
+
+mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
+                    size_t half, hipStream_t st);
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kParts = 1024;  // blocks of the first reduction stage
+
+struct Scalars {
+  double alpha, beta, rhobar, phibar;
+  double cx, cw;        // x += cx w ; w = v + cw w
+  double inv;           // reciprocal of the last norm (or 1 when it was 0)
+  double pad;
+  double part[kParts];  // stage-1 partial sums
+};
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;  // valid in thread 0
+}
+
+// out = a * x + coef * y  (coef = sgn * *cptr, or sgn when cptr is NULL); partial sum of out^2
+__global__ __launch_bounds__(kThreads) void lin_norm(float* out, const float* x, const float* y, const double* __restrict__ cptr,
+                                                     double sgn, size_t n, Scalars* sc) {
+  __shared__ double sh[kThreads / 64];
+  const float coef = (float)(cptr ? sgn * *cptr : sgn);
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    const float v = x[i] + coef * y[i];
+    out[i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) sc->part[blockIdx.x] = t;
+}
+
+// partial sums of x^2
+__global__ __launch_bounds__(kThreads) void sumsq(const float* __restrict__ x, size_t n, Scalars* sc) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+    acc += (double)x[i] * (double)x[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) sc->part[blockIdx.x] = t;
+}
+
+// norm = sqrt(sum of partials) into *dst; sc->inv = 1/norm (1 if norm == 0)
+__global__ __launch_bounds__(kThreads) void finish_norm(Scalars* sc, double* dst, int nparts) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += sc->part[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(t);
+    *dst = nrm;
+    sc->inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void scale_inv(float* __restrict__ x, size_t n, const Scalars* sc) {
+  const float s = (float)sc->inv;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) x[i] *= s;
+}
+
+// w = v, x = 0, phibar = beta, rhobar = alpha
+__global__ __launch_bounds__(kThreads) void init_xw(float* __restrict__ x, float* __restrict__ w,
+                                                    const float* __restrict__ v, size_t n, Scalars* sc,
+                                                    double* hist) {
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    x[i] = 0.f;
+    w[i] = v[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->phibar = sc->beta;
+    sc->rhobar = sc->alpha;
+    if (hist) hist[0] = sc->beta;
+  }
+}
+
+// Plane rotation of one LSQR step, in FP64, one thread.
+__global__ void givens(Scalars* sc, double* hist, int it) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double alpha = sc->alpha, beta = sc->beta, rhobar = sc->rhobar, phibar = sc->phibar;
+  const double rho = hypot(rhobar, beta);
+  if (rho > 0.0) {
+    const double c = rhobar / rho, s = beta / rho;
+    const double theta = s * alpha;
+    const double phi = c * phibar;
+    sc->rhobar = -c * alpha;
+    sc->phibar = s * phibar;
+    sc->cx = phi / rho;
+    sc->cw = -theta / rho;
+  } else {  // exact solution reached: leave x unchanged
+    sc->cx = 0.0;
+    sc->cw = 0.0;
+  }
+  if (hist) hist[it] = sc->phibar;
+}
+
+// x += cx w ; w = v + cw w
+__global__ __launch_bounds__(kThreads) void update_xw(float* __restrict__ x, float* __restrict__ w,
+                                                      const float* __restrict__ v, size_t n, const Scalars* sc) {
+  const float cx = (float)sc->cx, cw = (float)sc->cw;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    const float wi = w[i];
+    x[i] += cx * wi;
+    w[i] = v[i] + cw * wi;
+  }
+}
+
+inline int grid_for(size_t n) {
+  const size_t b = (n + kThreads - 1) / kThreads;
+  return (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
+}
+
+struct Sizes {
+  size_t model, data;  // element counts
+};
+
+Sizes sizes_of(const mdc_desc& d, const lsqr_desc& ld) {
+  Sizes z{};
+  if (ld.kind == MDC_OP_MARCHENKO) {
+    z.model = z.data = 2ull * d.nt * d.ns * ld.nv;
+  } else {
+    z.model = (size_t)d.nt * d.nr * ld.nv;
+    z.data = (size_t)d.nt * d.ns * ld.nv;
+  }
+  return z;
+}
+
+size_t work_bytes_of(const Sizes& z) {
+  size_t b = align_up(sizeof(Scalars), 256);
+  b += 2 * align_up(z.data * 4, 256);   // u, t
+  b += 3 * align_up(z.model * 4, 256);  // v, w, t2
+  return b;
+}
+
+}  // namespace
+
+mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld) {
+  if (!op || !ld) return fail(MDC_EINVAL, "NULL argument");
+  if (ld->kind != MDC_OP_MDC && ld->kind != MDC_OP_MARCHENKO) return fail(MDC_EINVAL, "unknown operator kind");
+  if (ld->niter < 0) return fail(MDC_EINVAL, "niter must be >= 0");
+  if (ld->kind == MDC_OP_MARCHENKO) {
+    if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko needs ns == nr");
+    if (ld->nv < 1 || 2 * ld->nv > d.max_cols) return fail(MDC_EINVAL, "2*nv outside [2, max_cols]");
+    if (!ld->onset) return fail(MDC_EINVAL, "Marchenko needs onsets");
+  } else if (ld->nv < 1 || ld->nv > d.max_cols) {
+    return fail(MDC_EINVAL, "nv outside [1, max_cols]");
+  }
+  return MDC_OK;
+}
+
+size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld) { return work_bytes_of(sizes_of(d, ld)); }
+
+mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
+                    void* work, hipStream_t st) {
+  const Sizes z = sizes_of(d, ld);
+  char* p = static_cast<char*>(work);
+  Scalars* sc = reinterpret_cast<Scalars*>(p);
+  p += align_up(sizeof(Scalars), 256);
+  float* u = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
+  float* t = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
+  float* v = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  float* w = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  float* t2 = reinterpret_cast<float*>(p);
+  const int kind = ld.kind;
+  const size_t half = z.model / 2;  // Marchenko block size (model == data)
+  const int gd = grid_for(z.data), gm = grid_for(z.model);
+  mdc_status s;
+
+  // beta1 u1 = b
+  hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, u, b, b, (const double*)nullptr, 0.0, z.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
+  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, u, z.data, sc);
+  // alpha1 v1 = A^H u1
+  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, u, v, half, st)) != MDC_OK) return s;
+  hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
+  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
+  hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, x, w, v, z.model, sc, hist);
+  if ((s = check_launch("lsqr init")) != MDC_OK) return s;
+
+  for (int it = 1; it <= ld.niter; ++it) {
+    // beta u = A v - alpha u
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 0, v, t, half, st)) != MDC_OK) return s;
+    hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, u, t, u, &sc->alpha, -1.0, z.data, sc);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
+    hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, u, z.data, sc);
+    // alpha v = A^H u - beta v
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, u, t2, half, st)) != MDC_OK) return s;
+    hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, v, t2, v, &sc->beta, -1.0, z.model, sc);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
+    hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
+    hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, hist, it);
+    hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, x, w, v, z.model, sc);
+    if ((s = check_launch("lsqr iteration")) != MDC_OK) return s;
+  }
+  return MDC_OK;
+}
+
+}  // namespace mdc

@@ -1,0 +1,109 @@
+"""GPU parity of the Marchenko operator (Eq.5) and of device LSQR against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsqr as ol
+from oracle import marchenko as omc
+from oracle import mdc as om
+from oracle import power
+from paper_2011_11120_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def mdcmod(gpu):
+    from paper_2011_11120_amd import mdc
+    return mdc
+
+
+def marchenko_case(nt=64, nfmax=25, nx=6, nv=3, seed=0, q=0.5):
+    n = nx * nx
+    K = synth.random_complex_kernel(nfmax, n, n, seed=seed)
+    K *= q / max(power.spectral_norm(K[f], iters=80) for f in range(nfmax))
+    onset = (4 + (np.arange(n * nv) * 7) % (nt // 2 - 4)).reshape(n, nv).astype(np.int32)
+    return K, onset
+
+
+def op_for(mdcmod, K, nt, max_cols):
+    nf, ns, nr = K.shape
+    op = mdcmod.MdcOp(nt, nf, ns, nr, max_cols=max_cols)
+    op.set_kernel(dev(K, torch.complex64))
+    return op
+
+
+@pytest.mark.parametrize("nt,nfmax,nx,nv", [(64, 25, 6, 3), (128, 65, 5, 1), (256, 60, 8, 5)])
+def test_marchenko_forward_adjoint(mdcmod, nt, nfmax, nx, nv):
+    print(f"marchenko nt={nt} nfmax={nfmax} nx={nx} nv={nv}", flush=True)
+    K, onset = marchenko_case(nt, nfmax, nx, nv)
+    n = nx * nx
+    op = op_for(mdcmod, K, nt, 2 * nv)
+    a0, a1 = synth.gaussian((nt, n, nv), seed=1), synth.gaussian((nt, n, nv), seed=2)
+    g0, g1 = op.marchenko(dev(onset, torch.int32), dev(a0), dev(a1))
+    r0, r1 = omc.forward(K, onset, a0, a1)
+    assert relmax(host(g0), r0) < TOL and relmax(host(g1), r1) < TOL
+    h0, h1 = op.marchenko(dev(onset, torch.int32), dev(a0), dev(a1), adjoint=True)
+    s0, s1 = omc.adjoint(K, onset, a0, a1)
+    assert relmax(host(h0), s0) < TOL and relmax(host(h1), s1) < TOL
+
+
+def test_lsqr_mdc_matches_oracle(mdcmod):
+    nt, nfmax, n, nv, niter = 64, 20, 36, 2, 12
+    K = synth.random_complex_kernel(nfmax, n, n, seed=3)
+    op = op_for(mdcmod, K, nt, nv)
+    b = synth.gaussian((nt, n, nv), seed=4)
+    x, hist = op.lsqr(dev(b), niter, nv=nv)
+    xr, hr = ol.lsqr(lambda v: [om.mdc_forward(K, v[0])], lambda u: [om.mdc_adjoint(K, u[0])], [b], niter)
+    assert rel2(host(x), xr[0]) < TOL
+    assert np.max(np.abs(host(hist) - hr) / hr[0]) < TOL
+
+
+@pytest.mark.parametrize("niter", [0, 1, 15])
+def test_lsqr_marchenko_matches_oracle(mdcmod, niter):
+    nt, nfmax, nx, nv = 64, 25, 5, 2
+    K, onset = marchenko_case(nt, nfmax, nx, nv, seed=5)
+    n = nx * nx
+    op = op_for(mdcmod, K, nt, 2 * nv)
+    fd = synth.ricker_spikes(nt, n, nv)
+    d0, d1 = omc.data(K, onset, fd)
+    b = np.stack([d0, d1])
+    x, hist = op.lsqr(dev(b), niter, kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=dev(onset, torch.int32))
+    A = lambda v: list(omc.forward(K, onset, *v))
+    AH = lambda u: list(omc.adjoint(K, onset, *u))
+    xr, hr = ol.lsqr(A, AH, [d0, d1], niter)
+    xg = host(x)
+    if niter == 0:
+        assert np.all(xg == 0)
+    else:
+        assert rel2(xg, np.stack(xr)) < TOL
+    assert np.max(np.abs(host(hist) - hr) / hr[0]) < TOL
+
+
+def test_lsqr_zero_kernel_returns_data(mdcmod):
+    nt, nfmax, n, nv = 32, 10, 16, 1
+    K = np.zeros((nfmax, n, n), dtype=complex)
+    op = op_for(mdcmod, K, nt, 2)
+    onset = np.full((n, nv), 5, dtype=np.int32)
+    b = np.stack([synth.gaussian((nt, n, nv), seed=s) for s in (1, 2)])
+    x, hist = op.lsqr(dev(b), 3, kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=dev(onset, torch.int32))
+    assert relmax(host(x), b) < 1e-6
+    assert host(hist)[-1] < 1e-5 * host(hist)[0]
