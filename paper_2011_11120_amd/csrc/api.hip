@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -65,10 +66,21 @@ size_t store_bytes(const mdc_desc& d) {
   return 0;
 }
 
+// Streaming (GEMV-family) kernels up to kGemvMaxCols columns, matrix cores beyond.
+// MDC_PRODUCT=gemv|gemm in the environment forces one family (for tests).
+static constexpr int kGemvMaxCols = 8;
+
 mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* /*kscale*/, int adjoint,
                           const float2* in, float2* out, int ncols, hipStream_t st) {
   if (d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported by the product", (int)d.prec);
-  return gemv_launch(d, static_cast<const float2*>(kstore), kernel_ld(d.nr), adjoint, in, out, ncols, st);
+  bool use_gemm = ncols > kGemvMaxCols;
+  if (const char* e = getenv("MDC_PRODUCT")) {
+    if (!strcmp(e, "gemv")) use_gemm = false;
+    else if (!strcmp(e, "gemm")) use_gemm = true;
+  }
+  const float2* K = static_cast<const float2*>(kstore);
+  if (use_gemm) return gemm_launch(d, K, kernel_ld(d.nr), adjoint, in, out, ncols, st);
+  return gemv_launch(d, K, kernel_ld(d.nr), adjoint, in, out, ncols, st);
 }
 
 }  // namespace mdc

@@ -29,4 +29,7 @@ mdc_status synth_launch(const mdc_desc& d, const mdc_synth_desc& sd, const Store
 mdc_status gemv_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
                        int ncols, hipStream_t st);
 
+mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
+                       int ncols, hipStream_t st);
+
 }  // namespace mdc

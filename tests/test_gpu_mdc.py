@@ -211,3 +211,78 @@ def test_c2_dot_product(c2op):
     lhs = np.vdot(host(op.forward(dev(x))), y)
     rhs = np.vdot(x, host(op.adjoint(dev(y))))
     assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+
+
+# ------------------------------------------------------- matrix-core path ----
+GEMM_SHAPES = [
+    (64, 20, 40, 40, 9),        # just above the streaming range
+    (64, 25, 130, 66, 16),      # ragged 128-row tile, ragged 16-column slab
+    (128, 40, 129, 257, 33),    # odd nr (padded rows), ragged everything
+    (256, 60, 300, 200, 64),    # one full 64-column tile
+    (128, 30, 200, 130, 65),    # two column tiles, second with one column
+    (64, 20, 17, 300, 130),     # three column tiles, tiny ns
+]
+
+
+@pytest.mark.parametrize("shape", GEMM_SHAPES)
+def test_gemm_kernels_match_oracle(mdcmod, shape):
+    nt, nfmax, ns, nr, nv = shape
+    print(f"gemm shape {shape}", flush=True)
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=nt + nr)
+    op = make_op(mdcmod, K, nt, max_cols=nv)
+    x = synth.gaussian((nt, nr, nv), seed=3)
+    y = synth.gaussian((nt, ns, nv), seed=4)
+    yg = host(op.forward(dev(x)))
+    xg = host(op.adjoint(dev(y)))
+    assert relmax(yg, om.mdc_forward(K, x)) < TOL
+    assert relmax(xg, om.mdc_adjoint(K, y)) < TOL
+
+
+@pytest.mark.parametrize("nv", [1, 3, 8])
+def test_gemm_forced_for_few_columns(mdcmod, monkeypatch, nv):
+    """The matrix-core kernels on column counts the streaming kernels normally take."""
+    monkeypatch.setenv("MDC_PRODUCT", "gemm")
+    nt, nfmax, ns, nr = 128, 40, 150, 98
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=21)
+    op = make_op(mdcmod, K, nt, max_cols=nv)
+    x = synth.gaussian((nt, nr, nv), seed=5)
+    y = synth.gaussian((nt, ns, nv), seed=6)
+    assert relmax(host(op.forward(dev(x))), om.mdc_forward(K, x)) < TOL
+    assert relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y)) < TOL
+
+
+@pytest.mark.parametrize("nv", [9, 24])
+def test_gemv_forced_for_many_columns(mdcmod, monkeypatch, nv):
+    monkeypatch.setenv("MDC_PRODUCT", "gemv")
+    nt, nfmax, n = 64, 20, 70
+    K = synth.random_complex_kernel(nfmax, n, n, seed=22)
+    op = make_op(mdcmod, K, nt, max_cols=nv)
+    x = synth.gaussian((nt, n, nv), seed=7)
+    assert relmax(host(op.forward(dev(x))), om.mdc_forward(K, x)) < TOL
+
+
+# ---------------------------------------------------------------- c3 size ----
+def test_c3_full_size_sampled(mdcmod):
+    """nt=1024, nfmax=300, ns=nr=3600, nv=64 on the matrix cores; sampled (trace, point) pairs."""
+    spec = synth.KernelSpec(nt=1024, nfmax=300, nx=60)
+    n, nv = spec.n, 64
+    print("c3: generating kernel on device", flush=True)
+    op = mdcmod.MdcOp(spec.nt, spec.nfmax, n, n, max_cols=nv)
+    op.synth_kernel(spec)
+    x = synth.ricker_spikes(spec.nt, n, nv, dt=spec.dt)
+    y_in = synth.gaussian((spec.nt, n, nv), seed=2)
+    yg = op.forward(dev(x))
+    xg = op.adjoint(dev(y_in))
+    torch.cuda.synchronize()
+    idx = np.array([0, 127, 128, 1800, 3599])
+    vs = np.array([0, 31, 63])
+    allf, alln = np.arange(spec.nfmax), np.arange(n)
+    print("c3: oracle rows", flush=True)
+    yref = om.mdc_forward(synth.kernel_block(spec, allf, idx, alln), x[:, :, vs])
+    ysub = yg[:, idx][:, :, vs].cpu().numpy().astype(np.float64)
+    assert relmax(ysub, yref) < TOL
+    print("c3: oracle columns", flush=True)
+    xref = om.mdc_adjoint(synth.kernel_block(spec, allf, alln, idx), y_in[:, :, vs])
+    xsub = xg[:, idx][:, :, vs].cpu().numpy().astype(np.float64)
+    assert relmax(xsub, xref) < TOL
+    op.close()
