@@ -11,10 +11,12 @@
 //
 // Layout: each workgroup owns CB consecutive traces (consecutive (n, v)
 // columns of the [nt][n][nv] array), so every global access of a time row or
-// a spectral row is contiguous across lanes.  LDS holds z as [M][CB] complex.
-// Twiddles come from an FP64-built table rounded once to FP32:
-// tw[k] = exp(-2 pi i k / nt).
+// a spectral row is contiguous across lanes; with 16-byte vectors a thread
+// moves four traces of one time row.  All global loads of a thread are issued
+// before any is consumed.  LDS holds z as [M][CB] complex plus the twiddle
+// table tw[k] = exp(-2 pi i k / nt) (built in FP64, rounded once to FP32).
 #include <climits>
+#include <cmath>
 
 #include "common.hpp"
 
@@ -35,8 +37,7 @@ template <int DIR>
 __device__ __forceinline__ void bfly4(float2& a0, float2& a1, float2& a2, float2& a3) {
   const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
   const float2 t2 = cadd(a1, a3), d = csub(a1, a3);
-  // DIR * i * d
-  const float2 id = (DIR < 0) ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+  const float2 id = (DIR < 0) ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);  // DIR * i * d
   a0 = cadd(t0, t2);
   a2 = csub(t0, t2);
   a1 = cadd(t1, id);
@@ -44,8 +45,9 @@ __device__ __forceinline__ void bfly4(float2& a0, float2& a1, float2& a2, float2
 }
 
 // Complete M-point Stockham FFT (unnormalised) of the CB columns in lds[M][CB].
+// tws: twiddle table in LDS (nt = 2M entries).
 template <int M, int CB, int DIR>
-__device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_lds(float2* lds, const float2* tws, int tid) {
   constexpr int LOG = log2c<M>();
   int Ns = 1;
   if constexpr (LOG % 2 == 1) {
@@ -77,7 +79,7 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ 
   constexpr int NB = (M / 4) * CB;
   constexpr int BPT = (NB + kThreads - 1) / kThreads;
   for (; Ns < M; Ns *= 4) {
-    const int tstep = 2 * (M / (4 * Ns));  // tw index stride per unit of r*k
+    const int tstep = 2 * (M / (4 * Ns));  // table stride per unit of r*k
     float2 v[BPT][4];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
@@ -90,7 +92,7 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ 
         if (Ns > 1) {
 #pragma unroll
           for (int r = 1; r < 4; ++r) {
-            float2 w = tw[r * k * tstep];
+            float2 w = tws[r * k * tstep];
             if (DIR > 0) w = cconj(w);
             v[i][r] = cmul(v[i][r], w);
           }
@@ -114,139 +116,328 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ 
   }
 }
 
-template <int M, int CB>
+template <int M>
+__device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __restrict__ tw, int tid) {
+  for (int k = tid; k < 2 * M; k += kThreads) tws[k] = tw[k];
+}
+
+// ----------------------------------------------------------------- forward ---
+// VEC: Q % 4 == 0 and x 16-byte aligned (four traces per 16-byte load);
+// CONTIG: the spectrum of consecutive traces is contiguous (one segment), so
+// two bins of a trace pair go out as one 16-byte store.
+template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
     const float* __restrict__ x, const int* __restrict__ onset, int conj, const float2* __restrict__ tw,
     int nfmax, int n, int nv, int ldc, int c0, float scale, float2* __restrict__ spec) {
-  extern __shared__ float2 lds[];
+  extern __shared__ __attribute__((aligned(16))) float2 sh[];
+  float2* lds = sh;            // [M][CB]
+  float2* tws = sh + M * CB;   // [2M]
   constexpr int NT = 2 * M;
-  constexpr int ROWS = kThreads / CB;
   const int Q = n * nv;
   const int tid = threadIdx.x;
-  const int col = tid % CB;
-  const int q = blockIdx.x * CB + col;
-  const bool qok = q < Q;
-  const int on = (onset != nullptr && qok) ? onset[q] : INT_MAX;
+  const int q0 = blockIdx.x * CB;
+  stage_twiddles<M>(tws, tw, tid);
 
-  for (int m = tid / CB; m < M; m += ROWS) {
-    float a = 0.f, b = 0.f;
-    if (qok) {
-      a = x[(size_t)(2 * m) * Q + q];
-      b = x[(size_t)(2 * m + 1) * Q + q];
-      if (onset != nullptr) {
-        if (!in_window(2 * m, NT, on)) a = 0.f;
-        if (!in_window(2 * m + 1, NT, on)) b = 0.f;
+  if constexpr (VEC) {
+    constexpr int CG = CB / 4;                 // 4-trace groups per row
+    constexpr int TASKS = M * CG;              // (m, group) pairs
+    constexpr int TPT = (TASKS + kThreads - 1) / kThreads;
+    float4 ra[TPT], rb[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int task = tid + i * kThreads;
+      const int m = task / CG, g = task - (task / CG) * CG;
+      const int q = q0 + 4 * g;
+      ra[i] = rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (task < TASKS && q < Q) {  // Q % 4 == 0: the whole group is in range
+        ra[i] = *reinterpret_cast<const float4*>(x + (size_t)(2 * m) * Q + q);
+        rb[i] = *reinterpret_cast<const float4*>(x + (size_t)(2 * m + 1) * Q + q);
       }
     }
-    lds[m * CB + col] = make_float2(a, b);
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int task = tid + i * kThreads;
+      if (task >= TASKS) continue;
+      const int m = task / CG, g = task - (task / CG) * CG;
+      const int q = q0 + 4 * g;
+      float a[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+      float b[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+      if (onset != nullptr && q < Q) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int on = onset[q + h];
+          if (!in_window(2 * m, NT, on)) a[h] = 0.f;
+          if (!in_window(2 * m + 1, NT, on)) b[h] = 0.f;
+        }
+      }
+      float4* dst = reinterpret_cast<float4*>(&lds[m * CB + 4 * g]);
+      dst[0] = make_float4(a[0], b[0], a[1], b[1]);
+      dst[1] = make_float4(a[2], b[2], a[3], b[3]);
+    }
+  } else {
+    const int col = tid % CB;
+    const int q = q0 + col;
+    const bool qok = q < Q;
+    const int on = (onset != nullptr && qok) ? onset[q] : INT_MAX;
+    constexpr int ROWS = kThreads / CB;
+    constexpr int TPT = (M + ROWS - 1) / ROWS;
+    float ra[TPT], rb[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int m = tid / CB + i * ROWS;
+      ra[i] = rb[i] = 0.f;
+      if (m < M && qok) {
+        ra[i] = x[(size_t)(2 * m) * Q + q];
+        rb[i] = x[(size_t)(2 * m + 1) * Q + q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int m = tid / CB + i * ROWS;
+      if (m >= M) continue;
+      float a = ra[i], b = rb[i];
+      if (!in_window(2 * m, NT, on)) a = 0.f;
+      if (!in_window(2 * m + 1, NT, on)) b = 0.f;
+      lds[m * CB + col] = make_float2(a, b);
+    }
   }
   __syncthreads();
-  fft_lds<M, CB, -1>(lds, tw, tid);
+  fft_lds<M, CB, -1>(lds, tws, tid);
 
-  const int r = q / nv, v = q - (q / nv) * nv;
-  for (int k = tid / CB; k < nfmax; k += ROWS) {
-    const float2 zk = lds[(k & (M - 1)) * CB + col];
-    const float2 zc = cconj(lds[((M - k) & (M - 1)) * CB + col]);
-    const float2 e = cscale(cadd(zk, zc), 0.5f);
-    const float2 d = csub(zk, zc);
-    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
-    float2 X = cscale(cadd(e, cmul(tw[k], o)), scale);
-    if (conj) X = cconj(X);
-    if (qok) spec[((size_t)k * n + r) * ldc + c0 + v] = X;
+  // split step: X_k = E_k + exp(-2 pi i k / nt) O_k for k < nfmax, two traces per task
+  constexpr int CP = CB / 2;
+  for (int task = tid; task < nfmax * CP; task += kThreads) {
+    const int k = task / CP, p = task - (task / CP) * CP;
+    const float2 w = tws[k];
+    float2 X[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 2 * p + h;
+      const float2 zk = lds[(k & (M - 1)) * CB + col];
+      const float2 zc = cconj(lds[((M - k) & (M - 1)) * CB + col]);
+      const float2 e = cscale(cadd(zk, zc), 0.5f);
+      const float2 d = csub(zk, zc);
+      const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
+      X[h] = cscale(cadd(e, cmul(w, o)), scale);
+      if (conj) X[h] = cconj(X[h]);
+    }
+    const int q = q0 + 2 * p;
+    if (CONTIG) {
+      // one segment with ldc == nv: spec index k*Q + q; Q even keeps the pair aligned
+      if (q + 1 < Q) {
+        *reinterpret_cast<float4*>(spec + (size_t)k * Q + q) = make_float4(X[0].x, X[0].y, X[1].x, X[1].y);
+      } else if (q < Q) {
+        spec[(size_t)k * Q + q] = X[0];
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int qq = q + h;
+        if (qq < Q) {
+          const int r = qq / nv, v = qq - (qq / nv) * nv;
+          spec[((size_t)k * n + r) * ldc + c0 + v] = X[h];
+        }
+      }
+    }
   }
 }
 
-template <int M, int CB>
+// ----------------------------------------------------------------- inverse ---
+template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
     const float2* __restrict__ spec, int ldc, int c0, int conj, const float2* __restrict__ tw, int nfmax,
     int n, int nv, float scale, float* __restrict__ out, const float* __restrict__ ident,
     const int* __restrict__ onset, float sign) {
-  extern __shared__ float2 lds[];
+  extern __shared__ __attribute__((aligned(16))) float2 sh[];
+  float2* lds = sh;
+  float2* tws = sh + M * CB;
   constexpr int NT = 2 * M;
-  constexpr int ROWS = kThreads / CB;
   const int Q = n * nv;
   const int tid = threadIdx.x;
-  const int col = tid % CB;
-  const int q = blockIdx.x * CB + col;
-  const bool qok = q < Q;
-  const int r = q / nv, v = q - (q / nv) * nv;
+  const int q0 = blockIdx.x * CB;
+  stage_twiddles<M>(tws, tw, tid);
+  __syncthreads();
 
-  auto bin = [&](int k) -> float2 {
-    if (!qok || k >= nfmax) return make_float2(0.f, 0.f);
-    float2 X = spec[((size_t)k * n + r) * ldc + c0 + v];
-    if (conj) X.y = -X.y;
-    if (k == 0 || k == M) X.y = 0.f;  // the inverse real transform keeps only Re of DC/Nyquist
-    return X;
-  };
-  // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) exp(+2 pi i k / nt)
-  for (int k = tid / CB; k <= M / 2; k += ROWS) {
-    const float2 a = bin(k), b = bin(M - k);
-    {
-      const float2 e = cadd(a, cconj(b));
-      const float2 o = cmul(csub(a, cconj(b)), cconj(tw[k]));
-      lds[k * CB + col] = make_float2(e.x - o.y, e.y + o.x);
+  auto bin2 = [&](int k, int q, float2& X0, float2& X1) {
+    X0 = X1 = make_float2(0.f, 0.f);
+    if (k >= nfmax) return;
+    if (CONTIG) {
+      if (q + 1 < Q) {
+        const float4 v = *reinterpret_cast<const float4*>(spec + (size_t)k * Q + q);
+        X0 = make_float2(v.x, v.y);
+        X1 = make_float2(v.z, v.w);
+      } else if (q < Q) {
+        X0 = spec[(size_t)k * Q + q];
+      }
+    } else {
+      if (q < Q) X0 = spec[((size_t)k * n + q / nv) * ldc + c0 + q % nv];
+      if (q + 1 < Q) X1 = spec[((size_t)k * n + (q + 1) / nv) * ldc + c0 + (q + 1) % nv];
     }
-    if (k > 0 && k < M / 2) {
-      const float2 e = cadd(b, cconj(a));
-      const float2 o = cmul(csub(b, cconj(a)), cconj(tw[M - k]));
-      lds[(M - k) * CB + col] = make_float2(e.x - o.y, e.y + o.x);
+    if (conj) { X0.y = -X0.y; X1.y = -X1.y; }
+    if (k == 0 || k == M) { X0.y = 0.f; X1.y = 0.f; }  // only Re of DC and Nyquist
+  };
+  // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) exp(+2 pi i k / nt), two traces per task
+  constexpr int CP = CB / 2;
+  for (int task = tid; task < (M / 2 + 1) * CP; task += kThreads) {
+    const int k = task / CP, p = task - (task / CP) * CP;
+    const int q = q0 + 2 * p;
+    float2 a[2], b[2];
+    bin2(k, q, a[0], a[1]);
+    bin2(M - k, q, b[0], b[1]);
+    const float2 wk = cconj(tws[k]), wmk = cconj(tws[M - k]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 2 * p + h;
+      {
+        const float2 e = cadd(a[h], cconj(b[h]));
+        const float2 o = cmul(csub(a[h], cconj(b[h])), wk);
+        lds[k * CB + col] = make_float2(e.x - o.y, e.y + o.x);
+      }
+      if (k > 0 && k < M / 2) {
+        const float2 e = cadd(b[h], cconj(a[h]));
+        const float2 o = cmul(csub(b[h], cconj(a[h])), wmk);
+        lds[(M - k) * CB + col] = make_float2(e.x - o.y, e.y + o.x);
+      }
     }
   }
   __syncthreads();
-  fft_lds<M, CB, +1>(lds, tw, tid);
+  fft_lds<M, CB, +1>(lds, tws, tid);
 
-  if (!qok) return;
-  const int on = (onset != nullptr) ? onset[q] : INT_MAX;
-  for (int m = tid / CB; m < M; m += ROWS) {
-    const float2 z = lds[m * CB + col];
+  // y[2m] = Re z[m] / sqrt(nt), y[2m+1] = Im z[m] / sqrt(nt); epilogue out = ident + sign * Theta * y
+  if constexpr (VEC) {
+    constexpr int CG = CB / 4;
+    constexpr int TASKS = M * CG;
+    for (int task = tid; task < TASKS; task += kThreads) {
+      const int m = task / CG, g = task - (task / CG) * CG;
+      const int q = q0 + 4 * g;
+      if (q >= Q) continue;
+      const float4 z01 = *reinterpret_cast<const float4*>(&lds[m * CB + 4 * g]);
+      const float4 z23 = *reinterpret_cast<const float4*>(&lds[m * CB + 4 * g + 2]);
+      float e0[4] = {z01.x, z01.z, z23.x, z23.z};
+      float e1[4] = {z01.y, z01.w, z23.y, z23.w};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int t = 2 * m + h;
-      float val = (h == 0 ? z.x : z.y) * scale;
-      if (onset != nullptr && !in_window(t, NT, on)) val = 0.f;
-      val *= sign;
-      const size_t idx = (size_t)t * Q + q;
-      if (ident != nullptr) val += ident[idx];
-      out[idx] = val;
+      for (int h = 0; h < 4; ++h) {
+        e0[h] *= scale * sign;
+        e1[h] *= scale * sign;
+        if (onset != nullptr) {
+          const int on = onset[q + h];
+          if (!in_window(2 * m, NT, on)) e0[h] = 0.f;
+          if (!in_window(2 * m + 1, NT, on)) e1[h] = 0.f;
+        }
+      }
+      const size_t i0 = (size_t)(2 * m) * Q + q, i1 = (size_t)(2 * m + 1) * Q + q;
+      float4 o0 = make_float4(e0[0], e0[1], e0[2], e0[3]);
+      float4 o1 = make_float4(e1[0], e1[1], e1[2], e1[3]);
+      if (ident != nullptr) {
+        const float4 d0 = *reinterpret_cast<const float4*>(ident + i0);
+        const float4 d1 = *reinterpret_cast<const float4*>(ident + i1);
+        o0 = make_float4(o0.x + d0.x, o0.y + d0.y, o0.z + d0.z, o0.w + d0.w);
+        o1 = make_float4(o1.x + d1.x, o1.y + d1.y, o1.z + d1.z, o1.w + d1.w);
+      }
+      *reinterpret_cast<float4*>(out + i0) = o0;
+      *reinterpret_cast<float4*>(out + i1) = o1;
+    }
+  } else {
+    const int col = tid % CB;
+    const int q = q0 + col;
+    if (q >= Q) return;
+    const int on = (onset != nullptr) ? onset[q] : INT_MAX;
+    for (int m = tid / CB; m < M; m += kThreads / CB) {
+      const float2 z = lds[m * CB + col];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = 2 * m + h;
+        float val = (h == 0 ? z.x : z.y) * scale * sign;
+        if (!in_window(t, NT, on)) val = 0.f;
+        const size_t idx = (size_t)t * Q + q;
+        if (ident != nullptr) val += ident[idx];
+        out[idx] = val;
+      }
     }
   }
 }
 
+// Columns per workgroup: wide blocks when there are many traces, narrow ones
+// (more workgroups) when there are few.
 template <int M>
-constexpr int cols_per_block() { return M >= 1024 ? 8 : 16; }
+int pick_cb(int Q) {
+  const int maxcb = (M >= 1024) ? 8 : 16;
+  if (Q >= 256 * 2 * maxcb) return maxcb;
+  return 4;
+}
+
+template <int M, int CB, bool VEC, bool CONTIG>
+mdc_status rfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const FftSeg& s, float2* spec,
+                    hipStream_t st) {
+  const int Q = n * nv;
+  const size_t lds = ((size_t)M * CB + 2 * M) * sizeof(float2);
+  const float scale = (float)(1.0 / std::sqrt((double)(2 * M)));
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)rfft_trunc_kernel<M, CB, VEC, CONTIG>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((rfft_trunc_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, s.in,
+                     s.onset, s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec);
+  return check_launch("rfft_trunc_kernel");
+}
+
+template <int M, int CB>
+mdc_status rfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const FftSeg& s, float2* spec,
+                   hipStream_t st) {
+  const int Q = n * nv;
+  const bool vec = (Q % 4 == 0) && aligned(s.in, 16);
+  const bool contig = (ldc == nv) && (Q % 2 == 0) && aligned(spec, 16);
+  if (vec && contig) return rfft_run<M, CB, true, true>(tw, nfmax, n, nv, ldc, s, spec, st);
+  if (vec) return rfft_run<M, CB, true, false>(tw, nfmax, n, nv, ldc, s, spec, st);
+  if (contig) return rfft_run<M, CB, false, true>(tw, nfmax, n, nv, ldc, s, spec, st);
+  return rfft_run<M, CB, false, false>(tw, nfmax, n, nv, ldc, s, spec, st);
+}
 
 template <int M>
 mdc_status rfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const FftSeg& s, float2* spec,
                     hipStream_t st) {
-  constexpr int CB = cols_per_block<M>();
+  constexpr int WIDE = (M >= 1024) ? 8 : 16;
+  if (pick_cb<M>(n * nv) == WIDE) return rfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
+  return rfft_cb<M, 4>(tw, nfmax, n, nv, ldc, s, spec, st);
+}
+
+template <int M, int CB, bool VEC, bool CONTIG>
+mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const IfftSeg& s, const float2* spec,
+                     hipStream_t st) {
   const int Q = n * nv;
-  const size_t lds = (size_t)M * CB * sizeof(float2);
+  const size_t lds = ((size_t)M * CB + 2 * M) * sizeof(float2);
+  const float scale = (float)(1.0 / std::sqrt((double)(2 * M)));
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)rfft_trunc_kernel<M, CB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void*)irfft_pad_kernel<M, CB, VEC, CONTIG>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr = true;
   }
-  const float scale = (float)(1.0 / __builtin_sqrt((double)(2 * M)));
-  hipLaunchKernelGGL((rfft_trunc_kernel<M, CB>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, s.in, s.onset,
-                     s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec);
-  return check_launch("rfft_trunc_kernel");
+  hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, spec,
+                     ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign);
+  return check_launch("irfft_pad_kernel");
+}
+
+template <int M, int CB>
+mdc_status irfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const IfftSeg& s, const float2* spec,
+                    hipStream_t st) {
+  const int Q = n * nv;
+  const bool vec = (Q % 4 == 0) && aligned(s.out, 16) && (s.ident == nullptr || aligned(s.ident, 16));
+  const bool contig = (ldc == nv) && (Q % 2 == 0) && aligned(spec, 16);
+  if (vec && contig) return irfft_run<M, CB, true, true>(tw, nfmax, n, nv, ldc, s, spec, st);
+  if (vec) return irfft_run<M, CB, true, false>(tw, nfmax, n, nv, ldc, s, spec, st);
+  if (contig) return irfft_run<M, CB, false, true>(tw, nfmax, n, nv, ldc, s, spec, st);
+  return irfft_run<M, CB, false, false>(tw, nfmax, n, nv, ldc, s, spec, st);
 }
 
 template <int M>
 mdc_status irfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const IfftSeg& s, const float2* spec,
                      hipStream_t st) {
-  constexpr int CB = cols_per_block<M>();
-  const int Q = n * nv;
-  const size_t lds = (size_t)M * CB * sizeof(float2);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void*)irfft_pad_kernel<M, CB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
-  }
-  const float scale = (float)(1.0 / __builtin_sqrt((double)(2 * M)));
-  hipLaunchKernelGGL((irfft_pad_kernel<M, CB>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, spec, ldc, s.c0,
-                     s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign);
-  return check_launch("irfft_pad_kernel");
+  constexpr int WIDE = (M >= 1024) ? 8 : 16;
+  if (pick_cb<M>(n * nv) == WIDE) return irfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
+  return irfft_cb<M, 4>(tw, nfmax, n, nv, ldc, s, spec, st);
 }
 
 }  // namespace

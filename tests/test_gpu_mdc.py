@@ -77,6 +77,8 @@ SHAPES = [
     (64, 25, 25, 25, 1),        # odd nr: padded rows
     (128, 40, 31, 129, 3),      # odd nr, ragged column tile
     (128, 30, 90, 258, 5),
+    (128, 40, 1030, 1030, 9),   # wide FFT blocks, n*nv not a multiple of 4 (scalar FFT path)
+    (64, 20, 2050, 2050, 4),    # wide FFT blocks, vector path, ragged last block
 ]
 
 
@@ -92,6 +94,20 @@ def test_random_kernels_match_oracle(mdcmod, shape):
     xg = host(op.adjoint(dev(y)))
     assert relmax(yg, om.mdc_forward(K, x)) < TOL
     assert relmax(xg, om.mdc_adjoint(K, y)) < TOL
+
+
+def test_unaligned_vectors_use_scalar_path(mdcmod):
+    nt, nfmax, n, nv = 64, 20, 40, 2
+    K = synth.random_complex_kernel(nfmax, n, n, seed=14)
+    op = make_op(mdcmod, K, nt, max_cols=nv)
+    x = synth.gaussian((nt, n, nv), seed=15)
+    buf = torch.zeros(x.size + 1, dtype=torch.float32, device="cuda")
+    xin = buf[1:]
+    xin.copy_(dev(x).reshape(-1))
+    obuf = torch.zeros(x.size + 1, dtype=torch.float32, device="cuda")
+    yout = obuf[1:]
+    mdcmod.mdc_forward(op.handle, xin, yout, nv)
+    assert relmax(host(yout).reshape(nt, n, nv), om.mdc_forward(K, x)) < TOL
 
 
 def test_gpu_dot_product_test(mdcmod):
