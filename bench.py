@@ -91,8 +91,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+                    help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload; "
+                         "c4: Marchenko LSQR solves (full, 2x, 4x decimated)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -108,6 +109,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     W = WORKLOAD
     spec = synth.KernelSpec(nt=W["nt"], nfmax=W["nfmax"], nx=W["nx"], dt=W["dt"], dx=W["dx"])
     n, nv = spec.n, W["nv"]
@@ -165,7 +168,7 @@ def main():
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_sha256_16") == source_hash(PRODUCT_SRC) and tr.get("workload") == W:
-            traffic = tr.get("bytes_per_launch")
+            traffic = round(tr["bytes_per_launch"] / 1e9, 4)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +193,8 @@ def main():
                    "kernel_GB": round(kbytes / 1e9, 4), "prec": "fp32", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_GB_per_launch": round(prod_bytes / 1e9, 4),
                      "kernel": "gemv_fwd_kernel / gemv_adj_kernel",
                      "avg_launch_ms": round(prod_ms, 5),
                      "stage_ms_per_launch": {k: round(ms_stage[i] / max(1, cnt[i]), 5) for i, k in
@@ -246,6 +251,49 @@ def bench_c3(args):
                                    enumerate(["rfft", "product_fwd", "product_adj", "irfft"])}}
     print(json.dumps(out), flush=True)
     op.close()
+
+
+def bench_c4(args, niter=30):
+    """Marchenko LSQR: nt=1024, nfmax=250, 50x50 traces, 32 points, 30 iterations, d = 1, 2, 4."""
+    import numpy as np
+    import torch
+    from paper_2011_11120_amd import mdc, workloads
+    res = {}
+    for d in (1, 2, 4):
+        case = workloads.marchenko_case(d=d, kappa_value=workloads.kappa("c4"))
+        op = mdc.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv)
+        op.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
+        on = torch.as_tensor(case.onset, dtype=torch.int32).cuda()
+        fd = torch.as_tensor(case.fd, dtype=torch.float32).cuda()
+        dg = op.marchenko_data(on, fd)
+        op.lsqr(dg, 2, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on)  # warm-up (allocates the work buffer)
+        torch.cuda.synchronize()
+        mdc.mdc_profile_read(op.handle)
+        mdc.mdc_profile(op.handle, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(max(1, args.steps)):
+            ev0.record()
+            x, hist = op.lsqr(dg, niter, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+            ev1.record()
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1) / 1e3)
+        mdc.mdc_profile(op.handle, False)
+        ms_stage, cnt = mdc.mdc_profile_read(op.handle)
+        h = hist.cpu().numpy()
+        n = case.n
+        prod_ms = (ms_stage[1] + ms_stage[2]) / max(1, cnt[1] + cnt[2])
+        flops = 8.0 * case.spec.nfmax * n * n * 2 * case.nv
+        res[f"d{d}"] = {"n": n, "s_per_solve": round(float(np.median(times)), 4),
+                        "solves_per_s": round(1.0 / float(np.median(times)), 3),
+                        "rel_residual": float(h[-1] / h[0]),
+                        "product_ms": round(prod_ms, 4), "product_TFLOPs": round(flops / prod_ms / 1e9, 2),
+                        "stage_ms_total": [round(v, 2) for v in ms_stage], "stage_counts": cnt}
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "Marchenko LSQR nt=1024 nfmax=250 50x50 grid nv=32 (N=64 fused) 30 it",
+                      "prec": "fp32 vectors, fp64 scalars", "results": res}), flush=True)
 
 
 if __name__ == "__main__":

@@ -149,6 +149,10 @@ mdc_status mch_forward(mdc_op* op, const int* onset, int nv, const float* in0, c
 mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1,
                        float* out0, float* out1, void* stream);
 
+/* Right-hand side of Eq.5: d0 = Theta R fd, d1 = 0, with fd [nt][n][nv] the
+ * direct (initial) focusing function; nv <= max_cols. */
+mdc_status mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float* d0, float* d1, void* stream);
+
 /* Per-stage timing with HIP events on the apply stream (for measurement).
  * enable != 0 starts recording; mdc_profile_read synchronises and returns the
  * summed milliseconds and launch counts of each stage since the last read:
@@ -184,6 +188,63 @@ mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_
  * norm estimate) after each iteration, or NULL; work: device workspace. */
 mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist,
                       void* work, size_t work_bytes, void* stream);
+
+/* -------------------------------------------------------------- serving ----
+ * A server runs Marchenko LSQR solves (Eq.5) for requests that arrive over
+ * time against one resident kernel (a square op over a full nx*nx grid).
+ * Every step is one pass over the kernel serving the columns of every admitted
+ * request (forward and adjoint steps alternate; each request advances one
+ * operator application per step), so concurrent requests share the kernel
+ * reads (Discussion: many focusing points per pass, independent groups of
+ * points).  Each request keeps its own Krylov vectors and FP64 scalars in a
+ * slot of the caller's arena; admission is FIFO by slot size and by the op's
+ * column budget (2*nv columns per request, max_cols in total).  A request
+ * draws its inputs on the device from its focusing points: direct traveltime
+ * td = |x_r - x_v| / c, window onsets max(rint(td/dt) - eps, 0), initial
+ * focusing function ricker_fp(lag(t) dt + td); decimation by 2 or 4 keeps the
+ * lattice traces of the paper's Sub2/Sub4 geometries with areal element d dx^2.
+ * A request's result depends only on its own columns (same alone or in a mix,
+ * up to the rounding of the product family chosen by the total width).
+ * The server owns the op and its workspace while it exists.  A worker thread
+ * and a HIP stream of the library run the steps. */
+typedef struct mdc_server mdc_server;
+typedef struct {
+  int nx;            /* grid side (nx*nx == op ns == op nr) */
+  double dx, dt;     /* trace spacing (m), time sampling (s) */
+  double c;          /* direct-arrival velocity (m/s) */
+  int eps;           /* window margin in samples */
+  double fp;         /* peak frequency of the initial focusing wavelet (Hz) */
+} serve_geometry;
+typedef struct {
+  int nv;                  /* focusing points, 1..64 */
+  int niter;               /* LSQR iterations, >= 0 */
+  int decim;               /* 1, 2 or 4 */
+  const double *vx, *vy, *vz;  /* host arrays of nv coordinates (m), copied at submit */
+  float* x_out;            /* device [2][nt][n][nv]: solution (f-, f_m+); ready when polled done */
+  double* hist;            /* device [niter+1] residual-norm history, or NULL */
+} serve_req;
+
+/* Arena bytes one request of nv points occupies. */
+mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes);
+/* arena: caller-owned device buffer (256-byte aligned) for request slots. */
+mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t arena_bytes, mdc_server** out);
+/* Queue a request (MDC_ENOMEM if it can never fit the arena or the column budget). Buffers
+ * must be ready (their producers synchronised) before the call. */
+mdc_status serve_submit(mdc_server* srv, const serve_req* req, uint64_t* id);
+/* done = 1 and MDC_OK when finished (latency = completion - submission, seconds);
+ * done = 0 and MDC_ENOTREADY while queued or running; done = -1 and MDC_ECANCELED. */
+mdc_status serve_poll(mdc_server* srv, uint64_t id, int* done, double* latency_s);
+/* Cancel a queued or running request; it leaves at the next step boundary. */
+mdc_status serve_cancel(mdc_server* srv, uint64_t id);
+/* Block until every submitted request has finished or been cancelled. */
+mdc_status serve_drain(mdc_server* srv);
+/* Completed solves per second (first submission to last completion), median and 99th
+ * percentile latency over completions after the first `skip`, completion count, the
+ * largest number of simultaneously admitted requests, and the number of steps run. */
+mdc_status serve_stats(mdc_server* srv, int skip, double* solves_per_s, double* p50_s, double* p99_s,
+                       int* completed, int* max_active, long* steps);
+/* Stop the worker (cancelling what is left) and release the handle. */
+mdc_status serve_destroy(mdc_server* srv);
 
 #ifdef __cplusplus
 }

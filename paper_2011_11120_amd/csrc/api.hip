@@ -12,23 +12,7 @@
 #include "common.hpp"
 #include "store.hpp"
 
-struct mdc_op {
-  mdc_desc d;
-  char* resident;
-  char* work;
-  float2* tw;        // [nt] exp(-2 pi i k / nt)
-  float* fscale;     // [nfmax] per-frequency storage scale (FP16S), else unused
-  void* kstore;      // stored kernel
-  float2* specR;     // [nfmax][nr][max_cols]
-  float2* specS;     // [nfmax][ns][max_cols]
-  bool kernel_ready;
-  std::vector<float2> tw_host;
-  // profiling
-  bool prof;
-  struct Ev { int stage; hipEvent_t a, b; };
-  std::vector<Ev> evs;
-  std::vector<hipEvent_t> pool;
-};
+
 
 namespace mdc {
 
@@ -231,7 +215,41 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
   return MDC_OK;
 }
 
-// Element-wise scaled conversion of a complex64 kernel into the resident store.
+__global__ void fill_zero(float* __restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
+// d0 = Theta R fd, d1 = 0 (right-hand side of the Marchenko system).
+mdc_status apply_mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float* d0, float* d1,
+                          hipStream_t st) {
+  const mdc_desc& d = op->d;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
+  if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
+  mdc_status s;
+  if ((s = check_vec(onset, "onset")) != MDC_OK) return s;
+  if ((s = check_vec(fd, "fd")) != MDC_OK) return s;
+  if ((s = check_vec(d0, "d0")) != MDC_OK) return s;
+  if ((s = check_vec(d1, "d1")) != MDC_OK) return s;
+  const int n = d.ns;
+  {
+    Stage t(op, 0, st);
+    FftSeg a{fd, nullptr, 0, 0};
+    if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, nv, a, op->specR, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, 1, st);
+    if ((s = product_launch(d, op->kstore, op->fscale, 0, op->specR, op->specS, nv, st)) != MDC_OK) return s;
+  }
+  {
+    Stage t(op, 3, st);
+    IfftSeg a{d0, nullptr, onset, 0, 0, 1.0f};
+    if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, nv, a, op->specS, st)) != MDC_OK) return s;
+  }
+  hipLaunchKernelGGL(fill_zero, dim3(1024), dim3(256), 0, st, d1, (size_t)d.nt * n * nv);
+  return check_launch("fill_zero");
+}
+
 // Element-wise scaled conversion of a complex64 kernel [nfmax*ns][nr] into the
 // resident store [nfmax*ns][ldk] (pad columns zero).
 __global__ void load_kernel_f32(const float2* __restrict__ K, float2* __restrict__ out, size_t count, int nr,
@@ -372,6 +390,11 @@ mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, c
                        float* out1, void* stream) {
   if (!op) return fail(MDC_EINVAL, "op is NULL");
   return apply_marchenko(op, onset, nv, in0, in1, out0, out1, 1, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float* d0, float* d1, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_mch_data(op, onset, nv, fd, d0, d1, static_cast<hipStream_t>(stream));
 }
 
 mdc_status mdc_profile(mdc_op* op, int enable) {

@@ -4,8 +4,28 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/mdc.h"
+
+// Operator state (host side; device buffers are caller-owned).
+struct mdc_op {
+  mdc_desc d;
+  char* resident;
+  char* work;
+  float2* tw;        // [nt] exp(-2 pi i k / nt)
+  float* fscale;     // [nfmax] per-frequency storage scale (FP16S), else unused
+  void* kstore;      // stored kernel
+  float2* specR;     // [nfmax][nr][max_cols]
+  float2* specS;     // [nfmax][ns][max_cols]
+  bool kernel_ready;
+  std::vector<float2> tw_host;
+  // profiling
+  bool prof;
+  struct Ev { int stage; hipEvent_t a, b; };
+  std::vector<Ev> evs;
+  std::vector<hipEvent_t> pool;
+};
 
 namespace mdc {
 
@@ -61,5 +81,19 @@ mdc_status irfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int 
 // adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].
 mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* kscale, int adjoint,
                           const float2* in, float2* out, int ncols, hipStream_t st);
+
+// Device state of one LSQR solve (all pointers are device memory).
+struct LsqrState {
+  void* sc;                    // FP64 scalars + reduction partials (lsqr_scalars_bytes())
+  float *u, *t, *v, *w, *t2;   // data-size u, t; model-size v, w, t2
+  float* x;                    // solution (model size)
+  double* hist;                // phibar history (niter + 1) or nullptr
+  size_t model, data;          // element counts
+};
+size_t lsqr_scalars_bytes();
+void lsqr_after_b(const LsqrState& s, hipStream_t st);
+void lsqr_after_init_adj(const LsqrState& s, hipStream_t st);
+void lsqr_after_fwd(const LsqrState& s, hipStream_t st);
+void lsqr_after_adj(const LsqrState& s, int it, hipStream_t st);
 
 }  // namespace mdc

@@ -136,6 +136,52 @@ inline int grid_for(size_t n) {
   return (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
 }
 
+}  // namespace
+
+size_t lsqr_scalars_bytes() { return align_up(sizeof(Scalars), 256); }
+
+// beta u = u (u holds b on entry)
+void lsqr_after_b(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gd = grid_for(s.data);
+  hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
+  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
+}
+
+// alpha v = t2 (= A^H u), w = v, x = 0
+void lsqr_after_init_adj(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gm = grid_for(s.model);
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.t2, (const double*)nullptr, 0.0,
+                     s.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
+  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, s.v, s.model, sc);
+  hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc, s.hist);
+}
+
+// beta u = t - alpha u  (t = A v)
+void lsqr_after_fwd(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gd = grid_for(s.data);
+  hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, s.u, s.t, s.u, &sc->alpha, -1.0, s.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
+  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
+}
+
+// alpha v = t2 - beta v  (t2 = A^H u); rotation; x += phi/rho w; w = v - theta/rho w
+void lsqr_after_adj(const LsqrState& s, int it, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gm = grid_for(s.model);
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.v, &sc->beta, -1.0, s.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
+  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, s.v, s.model, sc);
+  hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist, it);
+  hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
+}
+
+namespace {
+
 struct Sizes {
   size_t model, data;  // element counts
 };
@@ -152,7 +198,7 @@ Sizes sizes_of(const mdc_desc& d, const lsqr_desc& ld) {
 }
 
 size_t work_bytes_of(const Sizes& z) {
-  size_t b = align_up(sizeof(Scalars), 256);
+  size_t b = lsqr_scalars_bytes();
   b += 2 * align_up(z.data * 4, 256);   // u, t
   b += 3 * align_up(z.model * 4, 256);  // v, w, t2
   return b;
@@ -176,47 +222,41 @@ mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld) 
 
 size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld) { return work_bytes_of(sizes_of(d, ld)); }
 
+__global__ void copy_f32(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
                     void* work, hipStream_t st) {
   const Sizes z = sizes_of(d, ld);
   char* p = static_cast<char*>(work);
-  Scalars* sc = reinterpret_cast<Scalars*>(p);
-  p += align_up(sizeof(Scalars), 256);
-  float* u = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
-  float* t = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
-  float* v = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
-  float* w = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
-  float* t2 = reinterpret_cast<float*>(p);
+  LsqrState S{};
+  S.sc = p;
+  p += lsqr_scalars_bytes();
+  S.u = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
+  S.t = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
+  S.v = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  S.w = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  S.t2 = reinterpret_cast<float*>(p);
+  S.x = x;
+  S.hist = hist;
+  S.model = z.model;
+  S.data = z.data;
   const int kind = ld.kind;
   const size_t half = z.model / 2;  // Marchenko block size (model == data)
-  const int gd = grid_for(z.data), gm = grid_for(z.model);
   mdc_status s;
 
-  // beta1 u1 = b
-  hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, u, b, b, (const double*)nullptr, 0.0, z.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
-  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, u, z.data, sc);
-  // alpha1 v1 = A^H u1
-  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, u, v, half, st)) != MDC_OK) return s;
-  hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
-  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
-  hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, x, w, v, z.model, sc, hist);
+  hipLaunchKernelGGL(copy_f32, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.u, b, z.data);
+  lsqr_after_b(S, st);
+  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st)) != MDC_OK) return s;
+  lsqr_after_init_adj(S, st);
   if ((s = check_launch("lsqr init")) != MDC_OK) return s;
-
   for (int it = 1; it <= ld.niter; ++it) {
-    // beta u = A v - alpha u
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 0, v, t, half, st)) != MDC_OK) return s;
-    hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, u, t, u, &sc->alpha, -1.0, z.data, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
-    hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, u, z.data, sc);
-    // alpha v = A^H u - beta v
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, u, t2, half, st)) != MDC_OK) return s;
-    hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, v, t2, v, &sc->beta, -1.0, z.model, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
-    hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, v, z.model, sc);
-    hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, hist, it);
-    hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, x, w, v, z.model, sc);
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, st)) != MDC_OK) return s;
+    lsqr_after_fwd(S, st);
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st)) != MDC_OK) return s;
+    lsqr_after_adj(S, it, st);
     if ((s = check_launch("lsqr iteration")) != MDC_OK) return s;
   }
   return MDC_OK;

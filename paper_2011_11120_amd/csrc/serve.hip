@@ -1,0 +1,533 @@
+// Serving loop for Marchenko redatuming solves (Eq.5) against one resident kernel.
+//
+// The paper groups focusing points into independent inversions (Discussion:
+// embarrassingly parallel groups of points, each solved as one problem, and
+// many points per kernel pass because matrix-matrix products beat repeated
+// matrix-vector ones).  Here requests of uneven size (points, iterations,
+// decimation) arrive while others run; every step is one pass over the kernel
+// that serves the columns of every admitted request:
+//
+//   * the step direction alternates forward / adjoint; a request advances one
+//     operator application per step (data Theta R fd, then A^H u, then
+//     A v / A^H u per LSQR iteration), so all admitted requests share the pass;
+//   * each request's traces are transformed into its own column range of one
+//     spectral array, one product (GEMV or MFMA GEMM by total width) runs over
+//     all columns, and each request's inverse transform applies its own window,
+//     decimation scale and keep mask;
+//   * every request keeps its own FP64 LSQR scalars and Krylov vectors on the
+//     device, in a slot of the caller-provided arena; admission is FIFO by
+//     arena footprint and column budget; results of a request depend only on
+//     its own columns.
+//
+// Decimation by d is carried on the full grid: traces outside the lattice mask
+// have zero inputs, zero window, a zero keep mask on adjoint outputs, and R is
+// scaled by d (areal element d dx^2), which equals the decimated problem.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+
+namespace mdc {
+namespace {
+
+constexpr int kMaxPoints = 64;
+constexpr int kThreads = 256;
+
+struct PointArgs {
+  double vx[kMaxPoints], vy[kMaxPoints], vz[kMaxPoints];
+};
+
+__device__ __forceinline__ bool lattice_keep(int r, int nx, int d) {
+  const int ix = r / nx, iy = r - (r / nx) * nx;
+  if (d == 2) return ((ix + iy) & 1) == 0;
+  if (d == 4) return (((ix - iy) % 4) + 4) % 4 == 0;
+  return true;
+}
+
+// onset[r][v] = max(rint(td/dt) - eps, 0) on kept traces, 0 elsewhere; keep[r][v] = nt or 0;
+// fd[t][r][v] = ricker(lag(t) dt + td) on kept traces, 0 elsewhere; td = |x_r - x_v| / c (FP64,
+// no contraction, so the integer onsets match a host computation exactly).
+__global__ __launch_bounds__(kThreads) void request_inputs(int nt, int nx, double dx, double dt, double c, int eps,
+                                                           double fp, int d, int nv, PointArgs P,
+                                                           int* __restrict__ onset, int* __restrict__ keep,
+                                                           float* __restrict__ fd) {
+  const int n = nx * nx;
+  const size_t Q = (size_t)n * nv;
+  for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < (size_t)nt * Q; e += (size_t)gridDim.x * kThreads) {
+    const int t = (int)(e / Q);
+    const size_t q = e - (size_t)t * Q;
+    const int r = (int)(q / nv), v = (int)(q - (size_t)r * nv);
+    const bool kept = lattice_keep(r, nx, d);
+    const double rx = (double)(r / nx) * dx, ry = (double)(r % nx) * dx;
+    const double ax = __dadd_rn(rx, -P.vx[v]), ay = __dadd_rn(ry, -P.vy[v]);
+    const double h2 = __dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(P.vz[v], P.vz[v]));
+    const double td = __ddiv_rn(sqrt(h2), c);
+    if (t == 0) {
+      int o = (int)rint(__ddiv_rn(td, dt)) - eps;
+      o = o < 0 ? 0 : o;
+      onset[q] = kept ? o : 0;
+      keep[q] = kept ? nt : 0;
+    }
+    float val = 0.f;
+    if (kept) {
+      const double lag = (double)((2 * t < nt) ? t : t - nt) * dt;
+      const double a = M_PI * fp * (lag + td);
+      const double a2 = a * a;
+      val = (float)((1.0 - 2.0 * a2) * exp(-a2));
+    }
+    fd[e] = val;
+  }
+}
+
+__global__ void zero_f32(float* __restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
+enum Phase { kQueued, kData, kInitAdj, kIterF, kIterA, kDone, kCanceled };
+
+struct Request {
+  uint64_t id;
+  int nv, niter, decim;
+  PointArgs pts;
+  float* x_out;
+  double* hist;
+  size_t slot_off = 0, slot_bytes = 0;
+  int* onset = nullptr;
+  int* keep = nullptr;
+  LsqrState S{};
+  Phase phase = kQueued;
+  int it = 0;             // completed LSQR iterations
+  int c0 = 0;             // first spectral column in the current step
+  bool cancel = false;
+  bool finished = false;  // left the server (done or cancelled); set under the lock
+  std::chrono::steady_clock::time_point arrival, finish;
+};
+
+size_t slot_bytes_for(const mdc_desc& d, int nv) {
+  const size_t vec = 2ull * d.nt * d.ns * nv * 4;  // two Marchenko blocks
+  size_t b = 2 * align_up((size_t)d.ns * nv * 4, 256);  // onset, keep
+  b += lsqr_scalars_bytes();
+  b += 5 * align_up(vec, 256);                        // u, t, v, w, t2
+  return b;
+}
+
+// First-fit allocator over [0, size) with coalescing.
+class Arena {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+}  // namespace
+}  // namespace mdc
+
+using namespace mdc;
+
+struct mdc_server {
+  mdc_op* op = nullptr;
+  serve_geometry g{};
+  char* arena_base = nullptr;
+  size_t arena_bytes = 0;
+  Arena arena;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  bool stop = false;
+  uint64_t next_id = 1;
+  std::deque<Request*> queue;            // waiting for admission (FIFO)
+  std::vector<Request*> active;          // admitted, running
+  std::map<uint64_t, Request*> all;      // every request ever submitted
+  std::vector<double> latencies;         // completion order
+  std::chrono::steady_clock::time_point first_arrival, last_finish;
+  bool any_arrival = false;
+  int outstanding = 0;
+  int max_active = 0;
+  long steps = 0;
+  bool forward_next = true;
+  mdc_status error = MDC_OK;
+};
+
+namespace {
+
+int cols_for(const Request* r) { return r->phase == kData ? r->nv : 2 * r->nv; }
+
+bool wants_forward(const Request* r) { return r->phase == kData || r->phase == kIterF; }
+
+// Enqueue one fused step for the requests in `part` (all in the same direction).
+mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
+  mdc_op* op = S->op;
+  const mdc_desc& d = op->d;
+  const int n = d.ns;
+  hipStream_t st = S->stream;
+  int N = 0;
+  for (Request* r : part) {
+    r->c0 = N;
+    N += cols_for(r);
+  }
+  float2* spec_in = fwd ? op->specR : op->specS;
+  float2* spec_out = fwd ? op->specS : op->specR;
+  mdc_status s;
+  for (Request* r : part) {
+    const size_t half = (size_t)d.nt * n * r->nv;
+    if (r->phase == kData) {
+      FftSeg a{r->S.w, nullptr, 0, r->c0};  // fd was generated into w (block 0)
+      if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
+    } else if (fwd) {  // R on v1, R* on v0
+      FftSeg a{r->S.v + half, nullptr, 0, r->c0};
+      FftSeg b{r->S.v, nullptr, 1, r->c0 + r->nv};
+      if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
+      if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
+    } else {  // R^H on Theta u0, R*^H on Theta u1
+      FftSeg a{r->S.u, r->onset, 0, r->c0};
+      FftSeg b{r->S.u + half, r->onset, 1, r->c0 + r->nv};
+      if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
+      if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
+    }
+  }
+  if ((s = product_launch(d, op->kstore, op->fscale, fwd ? 0 : 1, spec_in, spec_out, N, st)) != MDC_OK) return s;
+  for (Request* r : part) {
+    const size_t half = (size_t)d.nt * n * r->nv;
+    const float dsc = (float)r->decim;
+    if (r->phase == kData) {  // u0 = d Theta R fd, u1 = 0 ; then beta u = b
+      IfftSeg a{r->S.u, nullptr, r->onset, 0, r->c0, dsc};
+      if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
+      hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, st, r->S.u + half, half);
+      lsqr_after_b(r->S, st);
+      r->phase = kInitAdj;
+    } else if (fwd) {  // t0 = v0 - d Theta R v1 ; t1 = v1 - d Theta R* v0
+      IfftSeg a{r->S.t, r->S.v, r->onset, 0, r->c0, -dsc};
+      IfftSeg b{r->S.t + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc};
+      if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
+      if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
+      lsqr_after_fwd(r->S, st);
+      r->phase = kIterA;
+    } else {  // t2_1 = u1 - d keep R^H Theta u0 ; t2_0 = u0 - d keep R*^H Theta u1
+      const int* km = r->decim > 1 ? r->keep : nullptr;
+      IfftSeg a{r->S.t2 + half, r->S.u + half, km, 0, r->c0, -dsc};
+      IfftSeg b{r->S.t2, r->S.u, km, 1, r->c0 + r->nv, -dsc};
+      if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
+      if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
+      if (r->phase == kInitAdj) {
+        lsqr_after_init_adj(r->S, st);
+        r->phase = r->niter > 0 ? kIterF : kDone;
+      } else {
+        r->it += 1;
+        lsqr_after_adj(r->S, r->it, st);
+        r->phase = r->it >= r->niter ? kDone : kIterF;
+      }
+    }
+  }
+  return check_launch("serve step");
+}
+
+// Give a request its arena slot and generate its inputs (called with the lock held).
+bool admit(mdc_server* S, Request* r) {
+  const mdc_desc& d = S->op->d;
+  size_t off;
+  const size_t bytes = slot_bytes_for(d, r->nv);
+  if (!S->arena.alloc(bytes, &off)) return false;
+  r->slot_off = off;
+  r->slot_bytes = bytes;
+  char* p = S->arena_base + off;
+  const size_t vec = 2ull * d.nt * d.ns * r->nv;
+  r->onset = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
+  r->keep = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
+  r->S.sc = p; p += lsqr_scalars_bytes();
+  r->S.u = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
+  r->S.t = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
+  r->S.v = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
+  r->S.w = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
+  r->S.t2 = reinterpret_cast<float*>(p);
+  r->S.x = r->x_out;
+  r->S.hist = r->hist;
+  r->S.model = r->S.data = vec;
+  hipLaunchKernelGGL(request_inputs, dim3(2048), dim3(kThreads), 0, S->stream, d.nt, S->g.nx, S->g.dx, S->g.dt,
+                     S->g.c, S->g.eps, S->g.fp, r->decim, r->nv, r->pts, r->onset, r->keep, r->S.w);
+  r->phase = kData;
+  return true;
+}
+
+void release(mdc_server* S, Request* r) {
+  if (r->slot_bytes) S->arena.release(r->slot_off, r->slot_bytes);
+  r->slot_bytes = 0;
+}
+
+void worker_main(mdc_server* S) {
+  hipSetDevice(S->device);
+  const int max_cols = S->op->d.max_cols;
+  while (true) {
+    std::vector<Request*> part;
+    bool fwd;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop) break;
+      // cancelled requests leave at step boundaries
+      for (auto it = S->active.begin(); it != S->active.end();) {
+        if ((*it)->cancel) {
+          (*it)->phase = kCanceled;
+          (*it)->finished = true;
+          release(S, *it);
+          S->outstanding -= 1;
+          it = S->active.erase(it);
+          S->done_cv.notify_all();
+        } else {
+          ++it;
+        }
+      }
+      if (S->active.empty()) S->forward_next = true;
+      fwd = S->forward_next;
+      if (fwd) {  // admission (new requests start with the forward data step)
+        int cols = 0;
+        for (Request* r : S->active) cols += 2 * r->nv;
+        while (!S->queue.empty()) {
+          Request* r = S->queue.front();
+          if (r->cancel) {
+            r->phase = kCanceled;
+            r->finished = true;
+            S->outstanding -= 1;
+            S->queue.pop_front();
+            S->done_cv.notify_all();
+            continue;
+          }
+          if (cols + 2 * r->nv > max_cols || !admit(S, r)) break;
+          cols += 2 * r->nv;
+          S->active.push_back(r);
+          S->queue.pop_front();
+        }
+      }
+      for (Request* r : S->active)
+        if (wants_forward(r) == fwd) part.push_back(r);
+      if ((int)S->active.size() > S->max_active) S->max_active = (int)S->active.size();
+      S->forward_next = !fwd;
+      if (part.empty()) continue;
+    }
+    mdc_status st = run_step(S, part, fwd);
+    // always wait for the step, also after a failed launch, before any slot can be reused
+    const hipError_t se = hipStreamSynchronize(S->stream);
+    if (st == MDC_OK && se != hipSuccess) st = fail(MDC_EDEVICE, "serve step failed: %s", hipGetErrorString(se));
+    const auto now = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->steps += 1;
+    if (st != MDC_OK) {  // fail every running request; the server stays up for new ones
+      S->error = st;
+      for (Request* r : part) r->phase = kCanceled;
+    }
+    for (auto it = S->active.begin(); it != S->active.end();) {
+      Request* r = *it;
+      if (r->phase == kDone || r->phase == kCanceled) {
+        r->finish = now;
+        r->finished = true;
+        if (r->phase == kDone) {
+          S->latencies.push_back(std::chrono::duration<double>(r->finish - r->arrival).count());
+          S->last_finish = now;
+        }
+        release(S, r);
+        S->outstanding -= 1;
+        it = S->active.erase(it);
+        S->done_cv.notify_all();
+      } else {
+        ++it;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes) {
+  if (!op || !bytes) return fail(MDC_EINVAL, "NULL argument");
+  if (nv < 1 || nv > kMaxPoints) return fail(MDC_EINVAL, "nv=%d outside [1, %d]", nv, kMaxPoints);
+  *bytes = slot_bytes_for(op->d, nv);
+  return MDC_OK;
+}
+
+mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t arena_bytes, mdc_server** out) {
+  if (!op || !g || !out) return fail(MDC_EINVAL, "NULL argument");
+  if (op->d.ns != op->d.nr) return fail(MDC_EINVAL, "serving needs a square operator (ns == nr)");
+  if (g->nx <= 0 || g->nx * g->nx != op->d.ns) return fail(MDC_EINVAL, "grid nx=%d does not match ns=%d", g->nx, op->d.ns);
+  if (!(g->dt > 0) || !(g->dx > 0) || !(g->c > 0) || g->eps < 0) return fail(MDC_EINVAL, "bad geometry");
+  if (!arena || !aligned(arena, 256)) return fail(MDC_EINVAL, "arena must be non-NULL and 256-byte aligned");
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  mdc_server* S = new (std::nothrow) mdc_server();
+  if (!S) return fail(MDC_ENOMEM, "host allocation failed");
+  S->op = op;
+  S->g = *g;
+  S->arena_base = static_cast<char*>(arena);
+  S->arena_bytes = arena_bytes / 256 * 256;
+  S->arena.reset(S->arena_bytes);
+  if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
+    delete S;
+    return fail(MDC_EDEVICE, "creating the serving stream failed");
+  }
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return MDC_OK;
+}
+
+mdc_status serve_submit(mdc_server* S, const serve_req* q, uint64_t* id) {
+  if (!S || !q || !id) return fail(MDC_EINVAL, "NULL argument");
+  if (q->nv < 1 || q->nv > kMaxPoints) return fail(MDC_EINVAL, "nv=%d outside [1, %d]", q->nv, kMaxPoints);
+  if (q->niter < 0) return fail(MDC_EINVAL, "niter must be >= 0");
+  if (q->decim != 1 && q->decim != 2 && q->decim != 4) return fail(MDC_EINVAL, "decimation must be 1, 2 or 4");
+  if (!q->vx || !q->vy || !q->vz) return fail(MDC_EINVAL, "virtual point arrays must not be NULL");
+  if (!q->x_out || !aligned(q->x_out, 16)) return fail(MDC_EINVAL, "x_out must be non-NULL and 16-byte aligned");
+  if (q->hist && !aligned(q->hist, 8)) return fail(MDC_EINVAL, "hist must be 8-byte aligned");
+  if (2 * q->nv > S->op->d.max_cols) return fail(MDC_ENOMEM, "2*nv=%d exceeds the column budget %d", 2 * q->nv, S->op->d.max_cols);
+  if (slot_bytes_for(S->op->d, q->nv) > S->arena_bytes)
+    return fail(MDC_ENOMEM, "request needs %zu bytes, the arena has %zu", slot_bytes_for(S->op->d, q->nv), S->arena_bytes);
+  Request* r = new (std::nothrow) Request();
+  if (!r) return fail(MDC_ENOMEM, "host allocation failed");
+  r->nv = q->nv;
+  r->niter = q->niter;
+  r->decim = q->decim;
+  for (int v = 0; v < q->nv; ++v) {
+    r->pts.vx[v] = q->vx[v];
+    r->pts.vy[v] = q->vy[v];
+    r->pts.vz[v] = q->vz[v];
+  }
+  r->x_out = q->x_out;
+  r->hist = q->hist;
+  r->arrival = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+      delete r;
+      return fail(MDC_EBUSY, "server is shutting down");
+    }
+    r->id = S->next_id++;
+    *id = r->id;
+    if (!S->any_arrival) {
+      S->first_arrival = r->arrival;
+      S->any_arrival = true;
+    }
+    S->all[r->id] = r;
+    S->queue.push_back(r);
+    S->outstanding += 1;
+  }
+  S->cv.notify_all();
+  return MDC_OK;
+}
+
+mdc_status serve_poll(mdc_server* S, uint64_t id, int* done, double* latency_s) {
+  if (!S || !done) return fail(MDC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return fail(MDC_EINVAL, "unknown request id %llu", (unsigned long long)id);
+  const Request* r = it->second;
+  if (!r->finished) {
+    *done = 0;
+    return MDC_ENOTREADY;
+  }
+  if (r->phase == kDone) {
+    *done = 1;
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->finish - r->arrival).count();
+    return MDC_OK;
+  }
+  *done = -1;
+  return fail(MDC_ECANCELED, "request %llu was cancelled or failed", (unsigned long long)id);
+}
+
+mdc_status serve_cancel(mdc_server* S, uint64_t id) {
+  if (!S) return fail(MDC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(id);
+  if (it == S->all.end()) return fail(MDC_EINVAL, "unknown request id %llu", (unsigned long long)id);
+  it->second->cancel = true;
+  S->cv.notify_all();
+  return MDC_OK;
+}
+
+mdc_status serve_drain(mdc_server* S) {
+  if (!S) return fail(MDC_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->done_cv.wait(lk, [&] { return S->outstanding == 0; });
+  return S->error == MDC_OK ? MDC_OK : fail(S->error, "a serving step failed");
+}
+
+mdc_status serve_stats(mdc_server* S, int skip, double* solves_per_s, double* p50_s, double* p99_s, int* completed,
+                       int* max_active, long* steps) {
+  if (!S) return fail(MDC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::vector<double> lat(S->latencies.begin() + std::min<size_t>(skip < 0 ? 0 : skip, S->latencies.size()),
+                          S->latencies.end());
+  if (completed) *completed = (int)S->latencies.size();
+  if (max_active) *max_active = S->max_active;
+  if (steps) *steps = S->steps;
+  if (solves_per_s) {
+    const double span = S->any_arrival ? std::chrono::duration<double>(S->last_finish - S->first_arrival).count() : 0.0;
+    *solves_per_s = span > 0 ? (double)S->latencies.size() / span : 0.0;
+  }
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double p) {
+    if (lat.empty()) return 0.0;
+    const double pos = p * (double)(lat.size() - 1);
+    const size_t i = (size_t)pos;
+    const double fr = pos - (double)i;
+    return i + 1 < lat.size() ? lat[i] * (1 - fr) + lat[i + 1] * fr : lat[i];
+  };
+  if (p50_s) *p50_s = pct(0.50);
+  if (p99_s) *p99_s = pct(0.99);
+  return MDC_OK;
+}
+
+mdc_status serve_destroy(mdc_server* S) {
+  if (!S) return MDC_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  hipStreamSynchronize(S->stream);
+  hipStreamDestroy(S->stream);
+  for (auto& kv : S->all) delete kv.second;
+  delete S;
+  return MDC_OK;
+}
+
+}  // extern "C"

@@ -47,6 +47,17 @@ class lsqr_desc(C.Structure):
     _fields_ = [("kind", C.c_int), ("nv", C.c_int), ("niter", C.c_int), ("onset", C.c_void_p)]
 
 
+class serve_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int), ("dx", C.c_double), ("dt", C.c_double), ("c", C.c_double),
+                ("eps", C.c_int), ("fp", C.c_double)]
+
+
+class serve_req(C.Structure):
+    _fields_ = [("nv", C.c_int), ("niter", C.c_int), ("decim", C.c_int),
+                ("vx", C.POINTER(C.c_double)), ("vy", C.POINTER(C.c_double)), ("vz", C.POINTER(C.c_double)),
+                ("x_out", C.c_void_p), ("hist", C.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2011_11120_amd.build (no CPU fallback)")
@@ -63,11 +74,21 @@ def _load():
         "mdc_adjoint": (st, [vp, vp, vp, i, vp]),
         "mch_forward": (st, [vp, vp, i, vp, vp, vp, vp, vp]),
         "mch_adjoint": (st, [vp, vp, i, vp, vp, vp, vp, vp]),
+        "mch_data": (st, [vp, vp, i, vp, vp, vp, vp]),
         "mdc_profile": (st, [vp, i]),
         "mdc_profile_read": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         "mdc_destroy": (st, [vp]),
         "lsqr_query_sizes": (st, [vp, C.POINTER(lsqr_desc), C.POINTER(C.c_size_t)]),
         "lsqr_solve": (st, [vp, C.POINTER(lsqr_desc), vp, vp, vp, vp, C.c_size_t, vp]),
+        "serve_request_bytes": (st, [vp, i, C.POINTER(C.c_size_t)]),
+        "serve_create": (st, [vp, C.POINTER(serve_geometry), vp, C.c_size_t, C.POINTER(vp)]),
+        "serve_submit": (st, [vp, C.POINTER(serve_req), C.POINTER(C.c_uint64)]),
+        "serve_poll": (st, [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+        "serve_cancel": (st, [vp, C.c_uint64]),
+        "serve_drain": (st, [vp]),
+        "serve_stats": (st, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                             C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_long)]),
+        "serve_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -78,8 +99,10 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", "mdc_synth_kernel",
-           "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mch_forward", "mch_adjoint",
-           "mdc_profile", "mdc_profile_read", "mdc_destroy", "lsqr_query_sizes", "lsqr_solve")
+           "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mch_forward", "mch_adjoint", "mch_data",
+           "mdc_profile", "mdc_profile_read", "mdc_destroy", "lsqr_query_sizes", "lsqr_solve",
+           "serve_request_bytes", "serve_create", "serve_submit", "serve_poll", "serve_cancel", "serve_drain",
+           "serve_stats", "serve_destroy")
 
 
 def _check(status: int):
@@ -151,6 +174,10 @@ def mch_adjoint(h, onset, nv, in0, in1, out0, out1, stream=None):
                             _stream(stream)))
 
 
+def mch_data(h, onset, nv, fd, d0, d1, stream=None):
+    _check(_lib.mch_data(h, _ptr(onset), int(nv), _ptr(fd), _ptr(d0), _ptr(d1), _stream(stream)))
+
+
 def mdc_profile(h, enable: bool):
     _check(_lib.mdc_profile(h, 1 if enable else 0))
 
@@ -175,6 +202,101 @@ def lsqr_query_sizes(h, ld: lsqr_desc) -> int:
 def lsqr_solve(h, ld: lsqr_desc, b, x, hist, work, stream=None):
     _check(_lib.lsqr_solve(h, C.byref(ld), _ptr(b), _ptr(x), _ptr(hist), _ptr(work),
                            C.c_size_t(work.numel() * work.element_size()), _stream(stream)))
+
+
+def serve_request_bytes(h, nv) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.serve_request_bytes(h, int(nv), C.byref(n)))
+    return n.value
+
+
+def serve_create(h, geom: serve_geometry, arena):
+    srv = C.c_void_p()
+    _check(_lib.serve_create(h, C.byref(geom), _ptr(arena), C.c_size_t(arena.numel() * arena.element_size()),
+                             C.byref(srv)))
+    return srv
+
+
+def serve_submit(srv, req: serve_req) -> int:
+    rid = C.c_uint64(0)
+    _check(_lib.serve_submit(srv, C.byref(req), C.byref(rid)))
+    return rid.value
+
+
+def serve_poll(srv, rid):
+    """Returns (done, latency_s): done = 1 finished, 0 running, -1 cancelled/failed."""
+    done, lat = C.c_int(0), C.c_double(0.0)
+    st = _lib.serve_poll(srv, C.c_uint64(rid), C.byref(done), C.byref(lat))
+    if st not in (MDC_OK, MDC_ENOTREADY, MDC_ECANCELED):
+        _check(st)
+    return done.value, lat.value
+
+
+def serve_cancel(srv, rid):
+    _check(_lib.serve_cancel(srv, C.c_uint64(rid)))
+
+
+def serve_drain(srv):
+    _check(_lib.serve_drain(srv))
+
+
+def serve_stats(srv, skip=0):
+    sps, p50, p99 = C.c_double(), C.c_double(), C.c_double()
+    done, mact, steps = C.c_int(), C.c_int(), C.c_long()
+    _check(_lib.serve_stats(srv, int(skip), C.byref(sps), C.byref(p50), C.byref(p99), C.byref(done),
+                            C.byref(mact), C.byref(steps)))
+    return {"solves_per_s": sps.value, "p50_s": p50.value, "p99_s": p99.value, "completed": done.value,
+            "max_active": mact.value, "steps": steps.value}
+
+
+def serve_destroy(srv):
+    _check(_lib.serve_destroy(srv))
+
+
+class Server:
+    """Owns the arena (PyTorch) and the library server over an MdcOp."""
+
+    def __init__(self, op, nx, arena_bytes, dx=20.0, dt=0.004, c=2000.0, eps=6, fp=20.0):
+        self.op = op
+        self.nt, self.n = op.nt, op.ns
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        self.handle = serve_create(op.handle, serve_geometry(nx, dx, dt, c, eps, fp), self.arena)
+        self._keep = {}
+
+    def submit(self, vx, vy, vz, niter, decim=1, x_out=None, hist=True):
+        import numpy as np
+        nv = len(vx)
+        if x_out is None:
+            x_out = torch.zeros((2, self.nt, self.n, nv), dtype=torch.float32, device="cuda")
+        h = torch.zeros(niter + 1, dtype=torch.float64, device="cuda") if hist else None
+        torch.cuda.synchronize()
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (vx, vy, vz)]
+        req = serve_req(nv, niter, decim, *[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs],
+                        x_out.data_ptr(), None if h is None else h.data_ptr())
+        rid = serve_submit(self.handle, req)
+        self._keep[rid] = (x_out, h)
+        return rid
+
+    def result(self, rid):
+        return self._keep[rid]
+
+    def poll(self, rid):
+        return serve_poll(self.handle, rid)
+
+    def cancel(self, rid):
+        serve_cancel(self.handle, rid)
+
+    def drain(self):
+        serve_drain(self.handle)
+
+    def stats(self, skip=0):
+        return serve_stats(self.handle, skip)
+
+    def close(self):
+        if self.handle is not None:
+            serve_destroy(self.handle)
+            self.handle = None
 
 
 # ------------------------------------------------------------ convenience ----
@@ -233,6 +355,12 @@ class MdcOp:
         o0, o1 = torch.empty_like(in0), torch.empty_like(in1)
         (mch_adjoint if adjoint else mch_forward)(self.handle, onset, nv, in0, in1, o0, o1)
         return o0, o1
+
+    def marchenko_data(self, onset, fd):
+        nv = onset.shape[1]
+        d = torch.empty((2,) + tuple(fd.shape), dtype=torch.float32, device=fd.device)
+        mch_data(self.handle, onset, nv, fd, d[0], d[1])
+        return d
 
     def lsqr(self, b, niter, kind=MDC_OP_MDC, nv=1, onset=None, hist=True):
         ld = lsqr_desc(kind, nv, niter, None if onset is None else onset.data_ptr())

@@ -154,11 +154,11 @@ class Events:
     v: np.ndarray
 
 
-def make_events(nev: int, T: float, seed: int = SEED_KERNEL) -> Events:
-    """nev events: amplitudes N(0,1); t0 ~ U(0.15T, 0.5T) and v ~ U(1500, 3000) m/s, both sorted."""
+def make_events(nev: int, T: float, seed: int = SEED_KERNEL, t0_lo: float = 0.15, t0_hi: float = 0.5) -> Events:
+    """nev events: amplitudes N(0,1); t0 ~ U(t0_lo T, t0_hi T) and v ~ U(1500, 3000) m/s, both sorted."""
     k = np.arange(nev)
     amp = rng_normal(seed, STREAM_EVENT_AMP, k)
-    t0 = np.sort(T * (0.15 + 0.35 * rng_uniform(seed, STREAM_EVENT_T0, k)))
+    t0 = np.sort(T * (t0_lo + (t0_hi - t0_lo) * rng_uniform(seed, STREAM_EVENT_T0, k)))
     v = np.sort(1500.0 + 1500.0 * rng_uniform(seed, STREAM_EVENT_V, k))
     return Events(amp, t0, v)
 
@@ -192,11 +192,14 @@ class KernelSpec:
     noise: float = 0.05
     kappa: float = 1.0
     seed: int = SEED_KERNEL
+    area_scale: float = 1.0
+    t0_lo: float = 0.15
+    t0_hi: float = 0.5
     events: Events = field(default=None)
 
     def __post_init__(self):
         if self.events is None:
-            self.events = make_events(self.nev, self.nt * self.dt, self.seed)
+            self.events = make_events(self.nev, self.nt * self.dt, self.seed, self.t0_lo, self.t0_hi)
 
     @property
     def n(self) -> int:
@@ -204,7 +207,8 @@ class KernelSpec:
 
     @property
     def dA(self) -> float:
-        return self.dx * self.dx
+        """Areal element of a trace: dx^2, times d for a grid decimated by d."""
+        return self.dx * self.dx * self.area_scale
 
 
 def kernel_block(spec: KernelSpec, f_idx, s_idx, r_idx) -> np.ndarray:

@@ -1,0 +1,146 @@
+"""Serving loop: per-request parity with the oracle, alone vs mix, admission, errors, cancel."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsqr as ol
+from oracle import marchenko as omc
+from paper_2011_11120_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+
+NX, NT, NF = 8, 64, 20
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def mdcmod(gpu):
+    from paper_2011_11120_amd import mdc
+    return mdc
+
+
+def spec_for(d):
+    # scale so that max_f ||K_f||_2 is about 0.4 on the 8 x 8 grid
+    base = workloads.marchenko_spec(nx=NX, nt=NT, nfmax=NF, d=1)
+    idx = np.arange(NX * NX)
+    K = synth.kernel_block(base, np.arange(NF), idx, idx)
+    kap = 0.4 / max(np.linalg.norm(K[f], 2) for f in range(NF))
+    return workloads.marchenko_spec(nx=NX, nt=NT, nfmax=NF, d=d, kappa_value=kap), kap
+
+
+@pytest.fixture(scope="module")
+def served(mdcmod):
+    spec, kap = spec_for(1)
+    op = mdcmod.MdcOp(NT, NF, NX * NX, NX * NX, max_cols=64)
+    op.synth_kernel(spec)
+    return op, kap
+
+
+def points(nv, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(20, 120, nv), rng.uniform(20, 120, nv), rng.uniform(100, 200, nv)
+
+
+def oracle_solution(kap, decim, vx, vy, vz, niter):
+    spec = workloads.marchenko_spec(nx=NX, nt=NT, nfmax=NF, d=decim, kappa_value=kap)
+    idx, onset, fd = workloads.serve_request_inputs(NX, NT, decim, vx, vy, vz)
+    K = synth.kernel_block(spec, np.arange(NF), idx, idx)
+    on, f = onset[idx], fd[:, idx]
+    d0, d1 = omc.data(K, on, f)
+    x, h = ol.lsqr(lambda v: list(omc.forward(K, on, *v)), lambda u: list(omc.adjoint(K, on, *u)), [d0, d1], niter)
+    return idx, np.stack(x), h
+
+
+REQS = [(1, 4, 1), (3, 6, 1), (2, 5, 2), (5, 3, 4), (1, 7, 2), (4, 2, 1)]
+
+
+def test_requests_in_a_mix_match_oracle(mdcmod, served):
+    op, kap = served
+    srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+    ids = []
+    for k, (nv, niter, decim) in enumerate(REQS):
+        vx, vy, vz = points(nv, k)
+        ids.append((srv.submit(vx, vy, vz, niter, decim), (nv, niter, decim, vx, vy, vz)))
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] == len(REQS) and st["max_active"] > 1
+    for rid, (nv, niter, decim, vx, vy, vz) in ids:
+        done, lat = srv.poll(rid)
+        assert done == 1 and lat > 0
+        x, h = srv.result(rid)
+        xg = x.cpu().numpy().astype(np.float64)
+        idx, xr, hr = oracle_solution(kap, decim, vx, vy, vz, niter)
+        print(f"request nv={nv} niter={niter} d={decim}: err {rel2(xg[:, :, idx], xr):.2e}", flush=True)
+        assert rel2(xg[:, :, idx], xr) < 1e-5
+        off = np.setdiff1d(np.arange(NX * NX), idx)
+        assert np.all(xg[:, :, off] == 0)
+        assert np.max(np.abs(h.cpu().numpy() - hr) / hr[0]) < 1e-5
+    srv.close()
+
+
+def test_alone_equals_mix(mdcmod, served):
+    op, kap = served
+    vx, vy, vz = points(3, 99)
+    alone = mdcmod.Server(op, NX, arena_bytes=1 << 28)
+    ra = alone.submit(vx, vy, vz, 5, 2)
+    alone.drain()
+    xa = alone.result(ra)[0].clone()
+    alone.close()
+    mix = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+    others = [mix.submit(*points(nv, 50 + k), 6, 1) for k, nv in enumerate((8, 16, 4))]
+    rm = mix.submit(vx, vy, vz, 5, 2)
+    mix.drain()
+    xm = mix.result(rm)[0]
+    assert mix.stats()["max_active"] >= 2
+    assert rel2(xm.cpu().numpy(), xa.cpu().numpy()) < 1e-5
+    mix.close()
+
+
+def test_admission_by_footprint(mdcmod, served):
+    op, kap = served
+    per = mdcmod.serve_request_bytes(op.handle, 4)
+    srv = mdcmod.Server(op, NX, arena_bytes=2 * per + per // 2)
+    ids = [srv.submit(*points(4, k), 3, 1) for k in range(5)]
+    srv.drain()
+    st = srv.stats()
+    assert st["completed"] == 5 and st["max_active"] == 2
+    for rid in ids:
+        assert srv.poll(rid)[0] == 1
+    with pytest.raises(mdcmod.MdcError) as ei:
+        srv.submit(*points(12, 1), 3, 1)  # needs more than the whole arena
+    assert ei.value.status == mdcmod.MDC_ENOMEM
+    srv.close()
+
+
+def test_column_budget_rejects_wide_requests(mdcmod):
+    spec, _ = spec_for(1)
+    op = mdcmod.MdcOp(NT, NF, NX * NX, NX * NX, max_cols=8)
+    op.synth_kernel(spec)
+    srv = mdcmod.Server(op, NX, arena_bytes=1 << 28)
+    with pytest.raises(mdcmod.MdcError) as ei:
+        srv.submit(*points(5, 1), 3, 1)  # 2 * 5 columns > 8
+    assert ei.value.status == mdcmod.MDC_ENOMEM
+    rid = srv.submit(*points(4, 1), 3, 1)
+    srv.drain()
+    assert srv.poll(rid)[0] == 1
+    srv.close()
+    op.close()
+
+
+def test_cancel_leaves_others_intact(mdcmod, served):
+    op, kap = served
+    srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+    keep_pts = points(2, 7)
+    long_id = srv.submit(*points(6, 3), 400, 1)
+    rid = srv.submit(*keep_pts, 4, 1)
+    srv.cancel(long_id)
+    srv.drain()
+    assert srv.poll(long_id)[0] == -1
+    assert srv.poll(rid)[0] == 1
+    x = srv.result(rid)[0].cpu().numpy().astype(np.float64)
+    idx, xr, _ = oracle_solution(kap, 1, *keep_pts, 4)
+    assert rel2(x[:, :, idx], xr) < 1e-5
+    srv.close()
