@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
                     help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload; "
                          "c4: Marchenko LSQR solves (full, 2x, 4x decimated)")
+    ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2"], default="fp32",
+                    help="kernel storage format for the c3/c4 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -213,7 +215,7 @@ def bench_c3(args):
     from paper_2011_11120_amd import mdc, synth
     spec = synth.KernelSpec(nt=1024, nfmax=300, nx=60)
     n, nv = spec.n, 64
-    op = mdc.MdcOp(spec.nt, spec.nfmax, n, n, max_cols=nv)
+    op = mdc.MdcOp(spec.nt, spec.nfmax, n, n, max_cols=nv, prec=args.prec)
     op.synth_kernel(spec)
     x = torch.as_tensor(synth.ricker_spikes(spec.nt, n, nv, dt=spec.dt), dtype=torch.float32).cuda()
     y = torch.as_tensor(synth.gaussian((spec.nt, n, nv)), dtype=torch.float32).cuda()
@@ -242,11 +244,19 @@ def bench_c3(args):
     flops = 8.0 * spec.nfmax * n * n * nv
     prod_ms = (ms_stage[1] + ms_stage[2]) / max(1, cnt[1] + cnt[2])
     tf = flops / (prod_ms * 1e-3) / 1e12
-    out = {"workload": "MDC GEMM nt=1024 nfmax=300 ns=nr=3600 nv=64, fwd+adj per step", "prec": "fp32",
+    kbytes = {"fp32": 8, "bf16x2": 8, "fp16s": 4, "bf16": 4}[args.prec] * spec.nfmax * n * n
+    if args.prec == "fp32":
+        roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": 157.3, "unit": "TFLOP/s", "frac": round(tf / 157.3, 4)}
+    else:  # split bf16 products: HBM-bound on the stored kernel bytes
+        gbs = kbytes / (prod_ms * 1e-3) / 1e9
+        nprod = 2 if args.prec == "bf16" else 3
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "mfma_bf16_TFLOPs": round(nprod * tf, 1), "mfma_bf16_frac": round(nprod * tf / 2500.0, 4)}
+    out = {"workload": "MDC GEMM nt=1024 nfmax=300 ns=nr=3600 nv=64, fwd+adj per step", "prec": args.prec,
            "ms_per_step": round(ms_step, 3), "product_ms": round(prod_ms, 3),
-           "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 157.3, "unit": "TFLOP/s",
-                        "frac": round(tf / 157.3, 4)},
-           "hbm_GBs_product": round(8.0 * spec.nfmax * n * n / (prod_ms * 1e-3) / 1e9, 1),
+           "complex_TFLOPs": round(tf, 2), "roofline": roof,
+           "hbm_GBs_product": round(kbytes / (prod_ms * 1e-3) / 1e9, 1),
            "stage_ms_per_launch": {k: round(ms_stage[i] / max(1, cnt[i]), 4) for i, k in
                                    enumerate(["rfft", "product_fwd", "product_adj", "irfft"])}}
     print(json.dumps(out), flush=True)
@@ -261,7 +271,7 @@ def bench_c4(args, niter=30):
     res = {}
     for d in (1, 2, 4):
         case = workloads.marchenko_case(d=d, kappa_value=workloads.kappa("c4"))
-        op = mdc.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv)
+        op = mdc.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv, prec=args.prec)
         op.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
         on = torch.as_tensor(case.onset, dtype=torch.int32).cuda()
         fd = torch.as_tensor(case.fd, dtype=torch.float32).cuda()
@@ -293,7 +303,7 @@ def bench_c4(args, niter=30):
         del op
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "Marchenko LSQR nt=1024 nfmax=250 50x50 grid nv=32 (N=64 fused) 30 it",
-                      "prec": "fp32 vectors, fp64 scalars", "results": res}), flush=True)
+                      "prec": f"kernel {args.prec}, fp32 vectors, fp64 scalars", "results": res}), flush=True)
 
 
 if __name__ == "__main__":

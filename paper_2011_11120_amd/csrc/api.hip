@@ -54,17 +54,18 @@ size_t store_bytes(const mdc_desc& d) {
 // MDC_PRODUCT=gemv|gemm in the environment forces one family (for tests).
 static constexpr int kGemvMaxCols = 8;
 
-mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* /*kscale*/, int adjoint,
+mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* kscale, int adjoint,
                           const float2* in, float2* out, int ncols, hipStream_t st) {
-  if (d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported by the product", (int)d.prec);
   bool use_gemm = ncols > kGemvMaxCols;
   if (const char* e = getenv("MDC_PRODUCT")) {
     if (!strcmp(e, "gemv")) use_gemm = false;
     else if (!strcmp(e, "gemm")) use_gemm = true;
   }
-  const float2* K = static_cast<const float2*>(kstore);
-  if (use_gemm) return gemm_launch(d, K, kernel_ld(d.nr), adjoint, in, out, ncols, st);
-  return gemv_launch(d, K, kernel_ld(d.nr), adjoint, in, out, ncols, st);
+  const int ldk = kernel_ld(d.nr);
+  if (!use_gemm) return gemv_launch(d, kstore, kscale, ldk, adjoint, in, out, ncols, st);
+  if (d.prec == MDC_FP32)
+    return gemm_launch(d, static_cast<const float2*>(kstore), ldk, adjoint, in, out, ncols, st);
+  return gemm16_launch(d, kstore, kscale, ldk, adjoint, in, out, ncols, st);
 }
 
 }  // namespace mdc
@@ -250,21 +251,35 @@ mdc_status apply_mch_data(mdc_op* op, const int* onset, int nv, const float* fd,
   return check_launch("fill_zero");
 }
 
-// Element-wise scaled conversion of a complex64 kernel [nfmax*ns][nr] into the
-// resident store [nfmax*ns][ldk] (pad columns zero).
-__global__ void load_kernel_f32(const float2* __restrict__ K, float2* __restrict__ out, size_t count, int nr,
-                                int ldk, double scale, const float* __restrict__ w) {
+// Scaled conversion of a complex64 kernel [nfmax][ns][nr] into the resident store
+// [nfmax][ns][ldk] (pad columns zero), through one of the storage formats.
+template <typename Store>
+__global__ void load_kernel(const float2* __restrict__ K, Store out, int nfmax, int ns, int nr, int ldk, double scale,
+                            const float* __restrict__ w) {
+  const size_t count = (size_t)nfmax * ns * ldk;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
     const size_t row = i / (size_t)ldk;
     const int r = (int)(i - row * (size_t)ldk);
-    float2 v = make_float2(0.f, 0.f);
+    const int f = (int)(row / (size_t)ns), s = (int)(row - (size_t)f * ns);
+    double re = 0.0, im = 0.0;
     if (r < nr) {
       const double m = scale * (w ? (double)w[r] : 1.0);
       const float2 k = K[row * nr + r];
-      v = make_float2((float)(k.x * m), (float)(k.y * m));
+      // round the scaled value to complex64 first, as a caller-scaled complex64 kernel would be
+      re = (double)(float)(k.x * m);
+      im = (double)(float)(k.y * m);
     }
-    out[i] = v;
+    out.put(f, s, r, re, im);
   }
+}
+
+template <typename Store>
+mdc_status launch_load(mdc_op* op, const float2* K, double scale, const float* w, hipStream_t st) {
+  const mdc_desc& d = op->d;
+  StoreRef ref{op->kstore, op->fscale, d.nfmax, d.ns, d.nr, kernel_ld(d.nr)};
+  hipLaunchKernelGGL(load_kernel<Store>, dim3(4096), dim3(256), 0, st, K, Store(ref), d.nfmax, d.ns, d.nr,
+                     kernel_ld(d.nr), scale, w);
+  return check_launch("load_kernel");
 }
 
 }  // namespace
@@ -336,13 +351,22 @@ mdc_status mdc_create(const mdc_desc* desc, void* resident, void* workspace, voi
 mdc_status mdc_set_kernel(mdc_op* op, const void* K, double scale, const float* col_weight, void* stream) {
   if (!op) return fail(MDC_EINVAL, "op is NULL");
   if (!K || !aligned(K, 8)) return fail(MDC_EINVAL, "K must be non-NULL and 8-byte aligned");
-  if (op->d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported yet", (int)op->d.prec);
-  const int ldk = kernel_ld(op->d.nr);
-  const size_t count = (size_t)op->d.nfmax * op->d.ns * ldk;
-  hipLaunchKernelGGL(load_kernel_f32, dim3(4096), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     static_cast<const float2*>(K), static_cast<float2*>(op->kstore), count, op->d.nr, ldk, scale,
-                     col_weight);
-  mdc_status s = check_launch("load_kernel_f32");
+  if (col_weight && !aligned(col_weight, 4)) return fail(MDC_EINVAL, "col_weight must be 4-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const float2* k = static_cast<const float2*>(K);
+  mdc_status s = MDC_OK;
+  switch (op->d.prec) {
+    case MDC_FP32: s = launch_load<StoreF32>(op, k, scale, col_weight, st); break;
+    case MDC_BF16: s = launch_load<StoreBF16>(op, k, scale, col_weight, st); break;
+    case MDC_BF16X2: s = launch_load<StoreBF16X2>(op, k, scale, col_weight, st); break;
+    case MDC_FP16S:
+      if (hipMemsetAsync(op->fscale, 0, (size_t)op->d.nfmax * 4, st) != hipSuccess)
+        return fail(MDC_EDEVICE, "clearing the scale table failed");
+      if ((s = launch_load<StoreMax>(op, k, scale, col_weight, st)) != MDC_OK) return s;
+      if ((s = fp16_scales_launch(op->fscale, op->d.nfmax, st)) != MDC_OK) return s;
+      s = launch_load<StoreF16S>(op, k, scale, col_weight, st);
+      break;
+  }
   if (s == MDC_OK) op->kernel_ready = true;
   return s;
 }
@@ -359,14 +383,51 @@ mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, flo
   if (!op || !re || !im) return fail(MDC_EINVAL, "NULL argument");
   const mdc_desc& d = op->d;
   if (f < 0 || f >= d.nfmax || s < 0 || s >= d.ns || r < 0 || r >= d.nr) return fail(MDC_EINVAL, "index out of range");
-  if (d.prec != MDC_FP32) return fail(MDC_ENOTSUP, "storage format %d not supported yet", (int)d.prec);
-  float2 v;
-  const float2* p = static_cast<const float2*>(op->kstore) + ((size_t)f * d.ns + s) * kernel_ld(d.nr) + r;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (hipMemcpyAsync(&v, p, sizeof v, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-    return fail(MDC_EDEVICE, "reading kernel element failed");
-  *re = v.x;
-  *im = v.y;
+  const int ldk = kernel_ld(d.nr);
+  const size_t row = (size_t)f * d.ns + s;
+  const char* base = static_cast<const char*>(op->kstore);
+  unsigned int w[2] = {0u, 0u};
+  float2 v{0.f, 0.f};
+  float sf = 1.f;
+  bool ok = true;
+  switch (d.prec) {
+    case MDC_FP32:
+      ok = hipMemcpyAsync(&v, base + (row * ldk + r) * 8, 8, hipMemcpyDeviceToHost, st) == hipSuccess;
+      break;
+    case MDC_FP16S:
+      ok = hipMemcpyAsync(&w[0], base + (row * ldk + r) * 4, 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+           hipMemcpyAsync(&sf, op->fscale + f, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+      break;
+    case MDC_BF16:
+      ok = hipMemcpyAsync(&w[0], base + (row * ldk + r) * 4, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+      break;
+    case MDC_BF16X2: {
+      const size_t g = row * (size_t)ldk * 8 + (size_t)(r >> 2) * 32 + (r & 3) * 4;
+      ok = hipMemcpyAsync(&w[0], base + g, 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+           hipMemcpyAsync(&w[1], base + g + 16, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+      break;
+    }
+  }
+  if (!ok || hipStreamSynchronize(st) != hipSuccess) return fail(MDC_EDEVICE, "reading kernel element failed");
+  auto bf = [](unsigned int h) {
+    const unsigned int u = h << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+  };
+  auto hf = [](unsigned int h) {
+    _Float16 x;
+    const unsigned short b = (unsigned short)h;
+    memcpy(&x, &b, 2);
+    return (float)x;
+  };
+  switch (d.prec) {
+    case MDC_FP32: *re = v.x; *im = v.y; break;
+    case MDC_FP16S: *re = hf(w[0] & 0xFFFFu) / sf; *im = hf(w[0] >> 16) / sf; break;
+    case MDC_BF16: *re = bf(w[0] & 0xFFFFu); *im = bf(w[0] >> 16); break;
+    case MDC_BF16X2: *re = bf(w[0] & 0xFFFFu) + bf(w[1] & 0xFFFFu); *im = bf(w[0] >> 16) + bf(w[1] >> 16); break;
+  }
   return MDC_OK;
 }
 

@@ -7,13 +7,17 @@
 // Adjoint  X_f[r][c] = sum_s conj(K_f[s][r]) Y_f[s][c]  (column sums)
 //
 // Forward: a wave owns RW rows at a time; lanes stride along the row with
-// 16-byte loads (two complex values), the column block of X_f sits in LDS
-// and is reused by the RW rows; a butterfly reduction across the wave closes
-// each row.  Adjoint: a workgroup owns 128 consecutive columns of K_f for all
-// rows (the "column-block ownership" layout), its four waves split the rows,
-// Y_f sits in LDS and is read as a broadcast, and the four partial sums are
-// added in a fixed order, so results are deterministic (no atomics).
+// 16-byte non-temporal loads (a group of VEC complex values: two in complex64,
+// four in a 16-bit format), the column block of X_f sits in LDS and is reused
+// by the RW rows; a butterfly reduction across the wave closes each row.
+// Adjoint: a workgroup owns 64*VEC consecutive columns of K_f for all rows
+// (column-block ownership), its four waves split the rows, Y_f sits in LDS and
+// is read as a broadcast, and the four partial sums are added in a fixed
+// order, so results are deterministic (no atomics).  16-bit formats are
+// widened to FP32 in registers; products accumulate in FP32; the FP16 format's
+// power-of-two frequency scale is divided out of each result.
 #include "common.hpp"
+#include "store.hpp"
 
 namespace mdc {
 namespace {
@@ -22,9 +26,55 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ldg_stream(const float4* p) {
-  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
+typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ vf4 ldnt_f4(const void* p) { return __builtin_nontemporal_load(static_cast<const vf4*>(p)); }
+__device__ __forceinline__ vu4 ldnt_u4(const void* p) { return __builtin_nontemporal_load(static_cast<const vu4*>(p)); }
+
+// Kernel formats: VEC complex values per 16-byte group (32 bytes for hi + lo).
+template <int FMT> struct KF;
+template <> struct KF<MDC_FP32> {
+  static constexpr int VEC = 2, GROUP_BYTES = 16;
+  __device__ static void load(const char* g, float2 (&k)[2]) {
+    const vf4 v = ldnt_f4(g);
+    k[0] = make_float2(v.x, v.y);
+    k[1] = make_float2(v.z, v.w);
+  }
+};
+template <> struct KF<MDC_FP16S> {
+  static constexpr int VEC = 4, GROUP_BYTES = 16;
+  __device__ static void load(const char* g, float2 (&k)[4]) {
+    const vu4 v = ldnt_u4(g);
+    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = make_float2(f16_bits_to_f(w[j] & 0xFFFFu), f16_bits_to_f(w[j] >> 16));
+  }
+};
+template <> struct KF<MDC_BF16> {
+  static constexpr int VEC = 4, GROUP_BYTES = 16;
+  __device__ static void load(const char* g, float2 (&k)[4]) {
+    const vu4 v = ldnt_u4(g);
+    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = make_float2(__uint_as_float(w[j] << 16), __uint_as_float(w[j] & 0xFFFF0000u));
+  }
+};
+template <> struct KF<MDC_BF16X2> {
+  static constexpr int VEC = 4, GROUP_BYTES = 32;
+  __device__ static void load(const char* g, float2 (&k)[4]) {
+    const vu4 h = ldnt_u4(g), l = ldnt_u4(g + 16);
+    const unsigned int wh[4] = {h.x, h.y, h.z, h.w}, wl[4] = {l.x, l.y, l.z, l.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      k[j] = make_float2(__uint_as_float(wh[j] << 16) + __uint_as_float(wl[j] << 16),
+                         __uint_as_float(wh[j] & 0xFFFF0000u) + __uint_as_float(wl[j] & 0xFFFF0000u));
+  }
+};
+
+template <int FMT>
+__device__ __forceinline__ float out_scale(const float* fscale, int f) {
+  if constexpr (FMT == MDC_FP16S) return 1.0f / fscale[f];  // exact: a power of two
+  else return 1.0f;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -34,21 +84,24 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // ---------------------------------------------------------------- forward ---
-// Requires nr even (16-byte aligned rows).  NC columns, RW rows per wave.
-template <int NC, int RW>
-__global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const float2* __restrict__ K,
-                                                            const float2* __restrict__ X,
-                                                            float2* __restrict__ Y, int ns, int nr, int ldk,
-                                                            int ldc, int col0, int groups_per_block, int rc) {
+template <int FMT, int NC, int RW>
+__global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restrict__ K, const float* __restrict__ fscale,
+                                                            const float2* __restrict__ X, float2* __restrict__ Y,
+                                                            int ns, int nr, int ldk, int ldc, int col0,
+                                                            int groups_per_block, int rc) {
+  using F = KF<FMT>;
+  constexpr int VEC = F::VEC;
   extern __shared__ float2 xs[];  // [rc][NC]
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const float2* Kf = K + (size_t)f * ns * ldk;
+  const size_t rowb = (size_t)(ldk / VEC) * F::GROUP_BYTES;
+  const char* Kf = K + (size_t)f * ns * rowb;
   const float2* Xf = X + (size_t)f * nr * ldc;
   float2* Yf = Y + (size_t)f * ns * ldc;
   const int nchunks = (ldk + rc - 1) / rc;
   const int rows_per_group = kWaves * RW;
+  const float osc = out_scale<FMT>(fscale, f);
 
   for (int g = 0; g < groups_per_block; ++g) {
     const int sbase = (blockIdx.x * groups_per_block + g) * rows_per_group + wave * RW;
@@ -61,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const float2* __rest
 
     for (int ch = 0; ch < nchunks; ++ch) {
       const int r0 = ch * rc;
-      const int rlen = min(rc, ldk - r0);  // even: ldk and rc are
+      const int rlen = min(rc, ldk - r0);  // a multiple of 4: ldk and rc are
       if (nchunks > 1 || g == 0) {
         __syncthreads();
         for (int e = threadIdx.x; e < rlen * NC; e += kThreads) {
@@ -70,23 +123,29 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const float2* __rest
         }
         __syncthreads();
       }
-      const int npos = rlen >> 1;  // float4 positions in this chunk
+      const int npos = rlen / VEC;
       for (int p = lane; p < npos; p += 64) {
-        float4 kv[RW];
+        float2 kv[RW][VEC];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
           const int s = sbase + i;
-          kv[i] = (s < ns) ? ldg_stream(reinterpret_cast<const float4*>(Kf + (size_t)s * ldk + r0) + p)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
+          if (s < ns) {
+            F::load(Kf + (size_t)s * rowb + (size_t)(r0 / VEC + p) * F::GROUP_BYTES, kv[i]);
+          } else {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) kv[i][j] = make_float2(0.f, 0.f);
+          }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const float2 x0 = xs[(2 * p) * NC + c];
-          const float2 x1 = xs[(2 * p + 1) * NC + c];
 #pragma unroll
-          for (int i = 0; i < RW; ++i) {
-            acc[i][c][0] += kv[i].x * x0.x - kv[i].y * x0.y + kv[i].z * x1.x - kv[i].w * x1.y;
-            acc[i][c][1] += kv[i].x * x0.y + kv[i].y * x0.x + kv[i].z * x1.y + kv[i].w * x1.x;
+          for (int j = 0; j < VEC; ++j) {
+            const float2 x = xs[(VEC * p + j) * NC + c];
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+              acc[i][c][0] += kv[i][j].x * x.x - kv[i][j].y * x.y;
+              acc[i][c][1] += kv[i][j].x * x.y + kv[i][j].y * x.x;
+            }
           }
         }
       }
@@ -98,33 +157,35 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const float2* __rest
         const float re = wave_sum(acc[i][c][0]);
         const float im = wave_sum(acc[i][c][1]);
         const int s = sbase + i;
-        if (lane == 0 && s < ns) Yf[(size_t)s * ldc + col0 + c] = make_float2(re, im);
+        if (lane == 0 && s < ns) Yf[(size_t)s * ldc + col0 + c] = make_float2(re * osc, im * osc);
       }
   }
 }
 
 // ---------------------------------------------------------------- adjoint ---
-// Requires nr even.  Workgroup = (column tile of 128, frequency).  UR rows of
-// K are loaded back to back by each wave before they are consumed.
-template <int NC, int UR>
-__global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const float2* __restrict__ K,
-                                                            const float2* __restrict__ Y,
-                                                            float2* __restrict__ X, int ns, int nr, int ldk,
-                                                            int ldc, int col0, int rcy) {
-  extern __shared__ float2 sh[];  // ys[rcy][NC], then partials [kWaves][64][2][NC]
+// Workgroup = (column tile of 64*VEC, frequency).  UR rows of K are loaded back
+// to back by each wave before they are consumed.
+template <int FMT, int NC, int UR>
+__global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restrict__ K, const float* __restrict__ fscale,
+                                                            const float2* __restrict__ Y, float2* __restrict__ X,
+                                                            int ns, int nr, int ldk, int ldc, int col0, int rcy) {
+  using F = KF<FMT>;
+  constexpr int VEC = F::VEC;
+  extern __shared__ float2 sh[];  // ys[rcy][NC], then partials [kWaves][VEC*NC*2][64]
   float2* ys = sh;
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const float2* Kf = K + (size_t)f * ns * ldk;
+  const size_t rowb = (size_t)(ldk / VEC) * F::GROUP_BYTES;
+  const char* Kf = K + (size_t)f * ns * rowb;
   const float2* Yf = Y + (size_t)f * ns * ldc;
   float2* Xf = X + (size_t)f * nr * ldc;
-  const int p = blockIdx.x * 64 + lane;  // float4 position = columns 2p, 2p+1
-  const bool pok = 2 * p < nr;
+  const int p = blockIdx.x * 64 + lane;  // group: columns VEC*p .. VEC*p + VEC-1
+  const bool pok = VEC * p < nr;
 
-  float acc[2][NC][2];
+  float acc[VEC][NC][2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < VEC; ++h)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[h][c][0] = acc[h][c][1] = 0.f;
 
@@ -136,15 +197,18 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const float2* __rest
       ys[e] = Yf[(size_t)(s0 + ss) * ldc + col0 + c];
     }
     __syncthreads();
-    // wave w takes rows w, w+4, w+8, ... of the chunk, UR at a time
+    // wave w takes rows w*UR .. w*UR+UR-1, then every kWaves*UR rows
     for (int sb = wave * UR; sb < slen; sb += kWaves * UR) {
-      float4 kv[UR];
+      float2 kv[UR][VEC];
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
         const int ss = sb + u;
-        kv[u] = (pok && ss < slen)
-                    ? ldg_stream(reinterpret_cast<const float4*>(Kf + (size_t)(s0 + ss) * ldk) + p)
-                    : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (pok && ss < slen) {
+          F::load(Kf + (size_t)(s0 + ss) * rowb + (size_t)p * F::GROUP_BYTES, kv[u]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < VEC; ++j) kv[u][j] = make_float2(0.f, 0.f);
+        }
       }
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
@@ -152,47 +216,50 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const float2* __rest
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const float2 y = ys[ss * NC + c];
-          // conj(k) * y = (kr yr + ki yi) + i (kr yi - ki yr)
-          acc[0][c][0] += kv[u].x * y.x + kv[u].y * y.y;
-          acc[0][c][1] += kv[u].x * y.y - kv[u].y * y.x;
-          acc[1][c][0] += kv[u].z * y.x + kv[u].w * y.y;
-          acc[1][c][1] += kv[u].z * y.y - kv[u].w * y.x;
+#pragma unroll
+          for (int h = 0; h < VEC; ++h) {
+            // conj(k) * y = (kr yr + ki yi) + i (kr yi - ki yr)
+            acc[h][c][0] += kv[u][h].x * y.x + kv[u][h].y * y.y;
+            acc[h][c][1] += kv[u][h].x * y.y - kv[u][h].y * y.x;
+          }
         }
       }
     }
   }
   // fixed-order reduction of the four waves' partials
   __syncthreads();
-  float* part = reinterpret_cast<float*>(sh);  // [kWaves][2*NC*2][64]
-  constexpr int NV = 2 * NC * 2;
+  float* part = reinterpret_cast<float*>(sh);
+  constexpr int NV = VEC * NC * 2;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < VEC; ++h)
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int z = 0; z < 2; ++z) part[(wave * NV + (h * NC + c) * 2 + z) * 64 + lane] = acc[h][c][z];
   __syncthreads();
   if (wave == 0 && pok) {
+    const float osc = out_scale<FMT>(fscale, f);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < VEC; ++h)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         float v[2];
 #pragma unroll
         for (int z = 0; z < 2; ++z) {
           const int k = ((h * NC + c) * 2 + z) * 64 + lane;
-          v[z] = ((part[k] + part[NV * 64 + k]) + (part[2 * NV * 64 + k] + part[3 * NV * 64 + k]));
+          v[z] = ((part[k] + part[NV * 64 + k]) + (part[2 * NV * 64 + k] + part[3 * NV * 64 + k])) * osc;
         }
-        if (2 * p + h < nr) Xf[(size_t)(2 * p + h) * ldc + col0 + c] = make_float2(v[0], v[1]);
+        if (VEC * p + h < nr) Xf[(size_t)(VEC * p + h) * ldc + col0 + c] = make_float2(v[0], v[1]);
       }
   }
 }
 
-template <int NC>
-mdc_status gemv_group(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
-                      int ldc, int col0, hipStream_t st) {
+template <int FMT, int NC>
+mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int ldk, int adjoint, const float2* in,
+                      float2* out, int ldc, int col0, hipStream_t st) {
+  constexpr int VEC = KF<FMT>::VEC;
   if (!adjoint) {
-    constexpr int RW = (NC >= 4) ? 2 : 4;
+    constexpr int RW = (NC * VEC >= 16) ? 2 : 4;
     const int rc = 4096 / NC;
     const int rows_per_group = kWaves * RW;
     const int ngroups = (d.ns + rows_per_group - 1) / rows_per_group;
@@ -200,37 +267,50 @@ mdc_status gemv_group(const mdc_desc& d, const float2* K, int ldk, int adjoint, 
     gpb = gpb < 1 ? 1 : (gpb > 8 ? 8 : gpb);
     const int nblk = (ngroups + gpb - 1) / gpb;
     const size_t lds = (size_t)rc * NC * sizeof(float2);
-    hipLaunchKernelGGL((gemv_fwd_kernel<NC, RW>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, in, out, d.ns,
-                       d.nr, ldk, ldc, col0, gpb, rc);
+    hipLaunchKernelGGL((gemv_fwd_kernel<FMT, NC, RW>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
+                       out, d.ns, d.nr, ldk, ldc, col0, gpb, rc);
     return check_launch("gemv_fwd_kernel");
   }
-  constexpr int UR = (NC >= 4) ? 4 : 8;
+  constexpr int UR = (NC * VEC >= 16) ? 4 : 8;
   const int rcy = 4096 / NC;
   const size_t lds_y = (size_t)rcy * NC * sizeof(float2);
-  const size_t lds_p = (size_t)kWaves * 2 * NC * 2 * 64 * sizeof(float);
+  const size_t lds_p = (size_t)kWaves * VEC * NC * 2 * 64 * sizeof(float);
   const size_t lds = lds_y > lds_p ? lds_y : lds_p;
-  const int nblk = ((d.nr + 1) / 2 + 63) / 64;
-  hipLaunchKernelGGL((gemv_adj_kernel<NC, UR>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, in, out, d.ns, d.nr,
-                     ldk, ldc, col0, rcy);
+  const int nblk = ((d.nr + VEC - 1) / VEC + 63) / 64;
+  hipLaunchKernelGGL((gemv_adj_kernel<FMT, NC, UR>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
+                     out, d.ns, d.nr, ldk, ldc, col0, rcy);
   return check_launch("gemv_adj_kernel");
 }
 
-}  // namespace
-
-// Few-column product (ncols columns in groups of 8, 4, 2, 1).
-mdc_status gemv_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
-                       int ncols, hipStream_t st) {
+template <int FMT>
+mdc_status gemv_fmt(const mdc_desc& d, const char* K, const float* fscale, int ldk, int adjoint, const float2* in,
+                    float2* out, int ncols, hipStream_t st) {
   int c0 = 0;
   while (c0 < ncols) {
     const int rem = ncols - c0;
     mdc_status s;
-    if (rem >= 8) { s = gemv_group<8>(d, K, ldk, adjoint, in, out, ncols, c0, st); c0 += 8; }
-    else if (rem >= 4) { s = gemv_group<4>(d, K, ldk, adjoint, in, out, ncols, c0, st); c0 += 4; }
-    else if (rem >= 2) { s = gemv_group<2>(d, K, ldk, adjoint, in, out, ncols, c0, st); c0 += 2; }
-    else { s = gemv_group<1>(d, K, ldk, adjoint, in, out, ncols, c0, st); c0 += 1; }
+    if (rem >= 8) { s = gemv_group<FMT, 8>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 8; }
+    else if (rem >= 4) { s = gemv_group<FMT, 4>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 4; }
+    else if (rem >= 2) { s = gemv_group<FMT, 2>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 2; }
+    else { s = gemv_group<FMT, 1>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 1; }
     if (s != MDC_OK) return s;
   }
   return MDC_OK;
+}
+
+}  // namespace
+
+// Few-column product (ncols columns in groups of 8, 4, 2, 1), any storage format.
+mdc_status gemv_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint, const float2* in,
+                       float2* out, int ncols, hipStream_t st) {
+  const char* k = static_cast<const char*>(K);
+  switch (d.prec) {
+    case MDC_FP32: return gemv_fmt<MDC_FP32>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+    case MDC_FP16S: return gemv_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+    case MDC_BF16: return gemv_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+    case MDC_BF16X2: return gemv_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+  }
+  return fail(MDC_EINVAL, "unknown storage format");
 }
 
 }  // namespace mdc

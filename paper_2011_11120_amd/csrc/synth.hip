@@ -119,8 +119,27 @@ mdc_status synth_launch(const mdc_desc& d, const mdc_synth_desc& sd, const Store
   }
   const dim3 grid((st_ref.ldk + 255) / 256, d.ns);
   switch (d.prec) {
-    case MDC_FP32: hipLaunchKernelGGL(synth_kernel<StoreF32>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index, StoreF32(st_ref)); break;
-    default: return fail(MDC_ENOTSUP, "synthetic kernel: storage format %d not supported", (int)d.prec);
+    case MDC_FP32:
+      hipLaunchKernelGGL(synth_kernel<StoreF32>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index, StoreF32(st_ref));
+      break;
+    case MDC_BF16:
+      hipLaunchKernelGGL(synth_kernel<StoreBF16>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index, StoreBF16(st_ref));
+      break;
+    case MDC_BF16X2:
+      hipLaunchKernelGGL(synth_kernel<StoreBF16X2>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index,
+                         StoreBF16X2(st_ref));
+      break;
+    case MDC_FP16S: {
+      // two passes: per-frequency maxima, power-of-two scales, then the scaled FP16 values
+      if (hipMemsetAsync(st_ref.fscale, 0, (size_t)d.nfmax * 4, st) != hipSuccess)
+        return fail(MDC_EDEVICE, "clearing the scale table failed");
+      hipLaunchKernelGGL(synth_kernel<StoreMax>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index, StoreMax(st_ref));
+      mdc_status s = check_launch("synth_kernel (max)");
+      if (s != MDC_OK) return s;
+      if ((s = fp16_scales_launch(st_ref.fscale, d.nfmax, st)) != MDC_OK) return s;
+      hipLaunchKernelGGL(synth_kernel<StoreF16S>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index, StoreF16S(st_ref));
+      break;
+    }
   }
   return check_launch("synth_kernel");
 }

@@ -1,0 +1,110 @@
+"""Reduced-precision kernel storage (FP16 with per-frequency power-of-two scale, BF16, BF16 hi+lo).
+
+Per-apply bound for the split low-precision formats: max-norm relative error <= 2e-3
+against the FP64 oracle; BF16 hi+lo keeps close to FP32 (<= 2e-5).  LSQR with a
+16-bit kernel: relative model error <= 1e-3 after the same iteration count.
+The error of each case is printed so the run log records it.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lsqr as ol
+from oracle import marchenko as omc
+from oracle import mdc as om
+from paper_2011_11120_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"bf16x2": 2e-5, "fp16s": 2e-3, "bf16": 8e-3}
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def mdcmod(gpu):
+    from paper_2011_11120_amd import mdc
+    return mdc
+
+
+SHAPES = [(64, 20, 40, 40, 1), (128, 40, 130, 98, 3), (128, 40, 129, 257, 9),
+          (256, 60, 300, 200, 64), (128, 30, 200, 130, 65), (64, 20, 70, 30, 17)]
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_formats_match_oracle(mdcmod, prec, shape):
+    nt, nfmax, ns, nr, nv = shape
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=ns + nv)
+    K *= np.exp(np.linspace(0, 8, nfmax))[:, None, None]  # spread magnitudes across frequencies
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    x = synth.gaussian((nt, nr, nv), seed=3)
+    y = synth.gaussian((nt, ns, nv), seed=4)
+    ef = relmax(host(op.forward(dev(x))), om.mdc_forward(K, x))
+    ea = relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y))
+    print(f"{prec} {shape}: forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef < TOL[prec] and ea < TOL[prec]
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16"])
+def test_formats_dot_product(mdcmod, prec):
+    """The forward and adjoint read the same stored kernel, so the pair stays adjoint."""
+    nt, nfmax, ns, nr, nv = 128, 40, 150, 90, 12
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=1)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    x = synth.gaussian((nt, nr, nv), seed=5)
+    y = synth.gaussian((nt, ns, nv), seed=6)
+    lhs = np.vdot(host(op.forward(dev(x))), y)
+    rhs = np.vdot(x, host(op.adjoint(dev(y))))
+    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 2.0 ** -15), ("fp16s", 2.0 ** -10), ("bf16", 2.0 ** -7)])
+def test_generator_formats(mdcmod, prec, tol):
+    spec = synth.KernelSpec(nt=256, nfmax=60, nx=12)
+    op = mdcmod.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, prec=prec)
+    op.synth_kernel(spec)
+    rng = np.random.default_rng(1)
+    for f, s, r in zip(rng.integers(1, 60, 40), rng.integers(0, 144, 40), rng.integers(0, 144, 40)):
+        ref = synth.kernel_block(spec, [f], [s], [r])[0, 0, 0]
+        got = mdcmod.mdc_kernel_element(op.handle, int(f), int(s), int(r))
+        assert abs(got.real - ref.real) <= tol * abs(ref.real) + 1e-12 * abs(ref)
+        assert abs(got.imag - ref.imag) <= tol * abs(ref.imag) + 1e-12 * abs(ref)
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s"])
+def test_marchenko_lsqr_low_precision(mdcmod, prec):
+    case = workloads.marchenko_case(nx=12, nt=256, nfmax=70, d=1, px=4, py=4,
+                                    kappa_value=workloads.kappa("c4") * 8.0)
+    op = mdcmod.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv, prec=prec)
+    op.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
+    on = dev(case.onset, torch.int32)
+    dg = op.marchenko_data(on, dev(case.fd))
+    x, _ = op.lsqr(dg, 20, kind=mdcmod.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+    K = synth.kernel_block(case.spec, np.arange(case.spec.nfmax), case.idx, case.idx)
+    d0, d1 = omc.data(K, case.onset, case.fd)
+    xr, _ = ol.lsqr(lambda v: list(omc.forward(K, case.onset, *v)),
+                    lambda u: list(omc.adjoint(K, case.onset, *u)), [d0, d1], 20)
+    err = rel2(host(x), np.stack(xr))
+    print(f"marchenko lsqr {prec}: model error {err:.2e}", flush=True)
+    assert err < 1e-3
+    op.close()
