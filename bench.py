@@ -91,9 +91,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload; "
-                         "c4: Marchenko LSQR solves (full, 2x, 4x decimated)")
+                         "c4: Marchenko LSQR solves (full, 2x, 4x decimated); c5: served stream of solves")
+    ap.add_argument("--requests", type=int, default=10, help="c5: requests per run")
+    ap.add_argument("--skip", type=int, default=2, help="c5: first completions left out of the latency stats")
+    ap.add_argument("--c5-precs", default="fp32,fp16s", help="c5: kernel formats to serve, in order")
     ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2"], default="fp32",
                     help="kernel storage format for the c3/c4 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -113,6 +116,8 @@ def main():
         return bench_c3(args)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
     W = WORKLOAD
     spec = synth.KernelSpec(nt=W["nt"], nfmax=W["nfmax"], nx=W["nx"], dt=W["dt"], dx=W["dx"])
     n, nv = spec.n, W["nv"]
@@ -304,6 +309,113 @@ def bench_c4(args, niter=30):
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "Marchenko LSQR nt=1024 nfmax=250 50x50 grid nv=32 (N=64 fused) 30 it",
                       "prec": f"kernel {args.prec}, fp32 vectors, fp64 scalars", "results": res}), flush=True)
+
+
+def c5_requests(R, seed=3):
+    """Seeded request mix: nv in [1, 64], iterations in [10, 60], decimation in {1, 2, 4};
+    focusing points are the first nv of an 8 x 8 grid (20 m) centred under the array at 650 m."""
+    import numpy as np
+    from paper_2011_11120_amd import synth
+    u = synth.rng_uniform(seed, synth.STREAM_SERVE, np.arange(4 * R)).reshape(R, 4)
+    vx, vy, vz = synth.virtual_points(100, 100, 20.0, 8, 8)
+    reqs = []
+    for k in range(R):
+        nv = 1 + int(u[k, 0] * 64)
+        niter = 10 + int(u[k, 1] * 51)
+        decim = (1, 2, 4)[int(u[k, 2] * 3)]
+        reqs.append(dict(nv=nv, niter=niter, decim=decim, vx=vx[:nv], vy=vy[:nv], vz=vz[:nv], u=float(u[k, 3])))
+    return reqs
+
+
+def serve_run(srv, reqs, rate=None, cap=6, keep=()):
+    """Submit requests (closed loop with at most `cap` outstanding, or Poisson arrivals at `rate`/s),
+    poll until all finish; returns per-request latencies and the kept solutions (host copies)."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    arrivals = []
+    if rate is not None:
+        acc = 0.0
+        for r in reqs:
+            acc += -np.log(1.0 - r["u"]) / rate  # exponential inter-arrival times from the seeded draw
+            arrivals.append(acc)
+    pending, out, kept = list(range(len(reqs))), {}, {}
+    live = {}
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and (len(live) < cap if rate is None else arrivals[pending[0]] <= now):
+            k = pending.pop(0)
+            r = reqs[k]
+            rid = srv.submit(r["vx"], r["vy"], r["vz"], r["niter"], r["decim"], hist=False)
+            live[rid] = k
+        for rid in list(live):
+            done, lat = srv.poll(rid)
+            if done != 0:
+                k = live.pop(rid)
+                out[k] = lat
+                if k in keep:
+                    kept[k] = srv.result(rid)[0].cpu()
+                srv._keep.pop(rid, None)
+                print(f"  request {k}: nv={reqs[k]['nv']} it={reqs[k]['niter']} d={reqs[k]['decim']} "
+                      f"latency {lat:.2f} s", file=sys.stderr, flush=True)
+        time.sleep(0.002)
+    torch.cuda.empty_cache()
+    return out, kept
+
+
+def bench_c5(args):
+    """Served stream: 100 x 100 traces, nfmax=200, nt=1024; FP32 vs 16-bit kernel storage."""
+    import numpy as np
+    import torch
+    from paper_2011_11120_amd import mdc, workloads
+    spec = workloads.marchenko_spec(nx=100, nt=1024, nfmax=200, kappa_value=workloads.kappa("c5"))
+    reqs = c5_requests(args.requests)
+    results, sols = {}, {}
+    rate = None
+    for prec in args.c5_precs.split(","):
+        op = mdc.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, max_cols=256, prec=prec)
+        op.synth_kernel(spec)
+        torch.cuda.synchronize()
+        free = torch.cuda.mem_get_info()[0]
+        out_bytes = 6 * 2 * spec.nt * spec.n * 64 * 4  # room for the outputs of 6 outstanding requests
+        arena = int(max(free - out_bytes - (6 << 30), 1 << 30))
+        arena_t = torch.empty(arena, dtype=torch.uint8, device="cuda")
+        srv = mdc.Server(op, 100, dx=spec.dx, dt=spec.dt, arena=arena_t)
+        print(f"{prec}: kernel {op.resident.numel() / 1e9:.1f} GB, arena {arena / 1e9:.1f} GB", file=sys.stderr,
+              flush=True)
+        res = {}
+        for mode in ("closed", "poisson"):
+            if mode == "poisson" and rate is None:
+                continue
+            t0 = time.perf_counter()
+            lat, kept = serve_run(srv, reqs, rate=rate if mode == "poisson" else None, keep=(0, 1))
+            st = srv.stats(skip=0)
+            srv.close()
+            srv = mdc.Server(op, 100, dx=spec.dx, dt=spec.dt, arena=arena_t)
+            l = np.array([lat[k] for k in sorted(lat)])[args.skip:]
+            res[mode] = {"solves_per_s": round(len(lat) / (time.perf_counter() - t0), 4),
+                         "p50_s": round(float(np.percentile(l, 50)), 3), "p99_s": round(float(np.percentile(l, 99)), 3),
+                         "max_active": st["max_active"], "steps": st["steps"]}
+            if mode == "closed":
+                sols[prec] = kept
+                if rate is None:
+                    rate = 0.7 * res[mode]["solves_per_s"]
+                    res[mode]["poisson_rate_set_here"] = round(rate, 4)
+        srv.close()
+        results[prec] = {"kernel_GB": round(op.resident.numel() / 1e9, 1), "arena_GB": round(arena / 1e9, 1), **res}
+        op.close()
+        del op, srv, arena_t
+        torch.cuda.empty_cache()
+    diff = {}
+    precs = args.c5_precs.split(",")
+    for p in precs[1:]:
+        diff[p] = {k: float(torch.linalg.vector_norm(sols[p][k] - sols[precs[0]][k]) /
+                            torch.linalg.vector_norm(sols[precs[0]][k])) for k in sols[p]}
+    print(json.dumps({"workload": "served Marchenko LSQR, 100x100 traces, nfmax=200, nt=1024, "
+                                  f"{len(reqs)} requests (nv 1-64, 10-60 it, d 1/2/4), first {args.skip} excluded",
+                      "requests": [{k: r[k] for k in ("nv", "niter", "decim")} for r in reqs],
+                      "results": results, "poisson_rate_per_s": rate,
+                      "solution_rel_diff_vs_" + precs[0]: diff}), flush=True)
 
 
 if __name__ == "__main__":

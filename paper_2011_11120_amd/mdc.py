@@ -256,10 +256,10 @@ def serve_destroy(srv):
 class Server:
     """Owns the arena (PyTorch) and the library server over an MdcOp."""
 
-    def __init__(self, op, nx, arena_bytes, dx=20.0, dt=0.004, c=2000.0, eps=6, fp=20.0):
+    def __init__(self, op, nx, arena_bytes=None, dx=20.0, dt=0.004, c=2000.0, eps=6, fp=20.0, arena=None):
         self.op = op
         self.nt, self.n = op.nt, op.ns
-        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self.arena = arena if arena is not None else torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         self.handle = serve_create(op.handle, serve_geometry(nx, dx, dt, c, eps, fp), self.arena)
         self._keep = {}
