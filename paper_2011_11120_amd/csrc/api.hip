@@ -509,6 +509,11 @@ mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x,
 
 mdc_status mdc_destroy(mdc_op* op) {
   if (!op) return MDC_OK;
+  if (op->lsqr_exec) hipGraphExecDestroy(op->lsqr_exec);
+  if (op->cap_stream) {
+    hipStreamSynchronize(op->cap_stream);
+    hipStreamDestroy(op->cap_stream);
+  }
   for (auto& e : op->evs) {
     hipEventDestroy(e.a);
     hipEventDestroy(e.b);

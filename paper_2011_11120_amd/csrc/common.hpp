@@ -8,6 +8,16 @@
 
 #include "../../include/mdc.h"
 
+// What a captured LSQR iteration graph depends on (pointers are baked into its nodes).
+struct LsqrGraphKey {
+  int kind, nv;
+  const void *onset, *work, *x, *hist, *b;
+  bool operator==(const LsqrGraphKey& o) const {
+    return kind == o.kind && nv == o.nv && onset == o.onset && work == o.work && x == o.x && hist == o.hist &&
+           b == o.b;
+  }
+};
+
 // Operator state (host side; device buffers are caller-owned).
 struct mdc_op {
   mdc_desc d;
@@ -25,6 +35,10 @@ struct mdc_op {
   struct Ev { int stage; hipEvent_t a, b; };
   std::vector<Ev> evs;
   std::vector<hipEvent_t> pool;
+  // LSQR iteration graph (captured on cap_stream, replayed on the caller's stream)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t lsqr_exec = nullptr;
+  LsqrGraphKey lsqr_key{};
 };
 
 namespace mdc {
@@ -94,6 +108,6 @@ size_t lsqr_scalars_bytes();
 void lsqr_after_b(const LsqrState& s, hipStream_t st);
 void lsqr_after_init_adj(const LsqrState& s, hipStream_t st);
 void lsqr_after_fwd(const LsqrState& s, hipStream_t st);
-void lsqr_after_adj(const LsqrState& s, int it, hipStream_t st);
+void lsqr_after_adj(const LsqrState& s, hipStream_t st);
 
 }  // namespace mdc

@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
           const int m = m0 + row, col = k0 + 4 * gi;
           if (m < ns && col < ldk)
             v = *reinterpret_cast<const u4v*>(Kf + (size_t)m * rowb + (size_t)(col >> 2) * 32 + half * 16);
-        } else {
-          const int srow = idx >> 6, c = idx & 63, gi = c >> 1, half = c & 1;
+        } else {  // consecutive lanes take consecutive kernel rows (conflict-free transposed LDS stores)
+          const int srow = idx & 31, c = idx >> 5, gi = c >> 1, half = c & 1;
           const int s = k0 + srow, col = m0 + 4 * gi;
           if (s < ns && col < ldk)
             v = *reinterpret_cast<const u4v*>(Kf + (size_t)s * rowb + (size_t)(col >> 2) * 32 + half * 16);
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
           const int m = m0 + row, col = k0 + 4 * c4;
           if (m < ns && col < ldk) v = *reinterpret_cast<const u4v*>(Kf + (size_t)m * rowb + (size_t)col * 4);
         } else {
-          const int srow = idx >> 5, c4 = idx & 31;
+          const int srow = idx & 31, c4 = idx >> 5;
           const int s = k0 + srow, col = m0 + 4 * c4;
           if (s < ns && col < ldk) v = *reinterpret_cast<const u4v*>(Kf + (size_t)s * rowb + (size_t)col * 4);
         }
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + kThreads * q;
-      const int krow = idx >> 5, c2 = idx & 31;
+      const int krow = idx & 31, c2 = idx >> 5;  // consecutive lanes: consecutive LDS words
       const int kk = k0 + krow, v = n0 + 2 * c2;
       const float2* src = Bf + (size_t)kk * ncols;
       pb[2 * q] = (kk < KD && v < ncols) ? src[v] : make_float2(0.f, 0.f);
@@ -137,16 +137,16 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
       unsigned int* dst_l;
       int rowl, coll;  // forward: (row, first column) ; adjoint: (first r, s)
       if constexpr (FMT == MDC_BF16X2) {
-        const int half = idx & 1;
+        const int half = ADJ ? ((idx >> 5) & 1) : (idx & 1);
         if (!ADJ) { rowl = idx >> 4; coll = 4 * ((idx & 15) >> 1); }
-        else { coll = idx >> 6; rowl = 4 * ((idx & 63) >> 1); }
+        else { coll = idx & 31; rowl = 4 * ((idx >> 5) >> 1); }
 #pragma unroll
         for (int h = 0; h < 4; ++h) hi[h] = w[h];
         dst_h = half ? Al : Ah;
         dst_l = nullptr;
       } else {
         if (!ADJ) { rowl = idx >> 3; coll = 4 * (idx & 7); }
-        else { coll = idx >> 5; rowl = 4 * (idx & 31); }
+        else { coll = idx & 31; rowl = 4 * (idx >> 5); }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
           if constexpr (FMT == MDC_FP16S) {
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + kThreads * q;
-      const int krow = idx >> 5, c2 = idx & 31;
+      const int krow = idx & 31, c2 = idx >> 5;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         unsigned int hi, lo;

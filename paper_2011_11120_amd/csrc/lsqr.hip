@@ -9,6 +9,7 @@
 // reduced in two fixed-shape stages (per-block FP64 partials, then one block),
 // so results do not depend on scheduling.
 #include <cmath>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -26,7 +27,7 @@ struct Scalars {
   double alpha, beta, rhobar, phibar;
   double cx, cw;        // x += cx w ; w = v + cw w
   double inv;           // reciprocal of the last norm (or 1 when it was 0)
-  double pad;
+  int iter, pad;        // completed iterations (device-side, so every iteration's launches are identical)
   double part[kParts];  // stage-1 partial sums
 };
 
@@ -96,13 +97,15 @@ __global__ __launch_bounds__(kThreads) void init_xw(float* __restrict__ x, float
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->phibar = sc->beta;
     sc->rhobar = sc->alpha;
+    sc->iter = 0;
     if (hist) hist[0] = sc->beta;
   }
 }
 
 // Plane rotation of one LSQR step, in FP64, one thread.
-__global__ void givens(Scalars* sc, double* hist, int it) {
+__global__ void givens(Scalars* sc, double* hist) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int it = ++sc->iter;
   const double alpha = sc->alpha, beta = sc->beta, rhobar = sc->rhobar, phibar = sc->phibar;
   const double rho = hypot(rhobar, beta);
   if (rho > 0.0) {
@@ -170,13 +173,13 @@ void lsqr_after_fwd(const LsqrState& s, hipStream_t st) {
 }
 
 // alpha v = t2 - beta v  (t2 = A^H u); rotation; x += phi/rho w; w = v - theta/rho w
-void lsqr_after_adj(const LsqrState& s, int it, hipStream_t st) {
+void lsqr_after_adj(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gm = grid_for(s.model);
   hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.v, &sc->beta, -1.0, s.model, sc);
   hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
   hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, s.v, s.model, sc);
-  hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist, it);
+  hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
   hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
 }
 
@@ -252,13 +255,53 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st)) != MDC_OK) return s;
   lsqr_after_init_adj(S, st);
   if ((s = check_launch("lsqr init")) != MDC_OK) return s;
-  for (int it = 1; it <= ld.niter; ++it) {
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, st)) != MDC_OK) return s;
-    lsqr_after_fwd(S, st);
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st)) != MDC_OK) return s;
-    lsqr_after_adj(S, it, st);
-    if ((s = check_launch("lsqr iteration")) != MDC_OK) return s;
+  auto iteration = [&](hipStream_t q) -> mdc_status {
+    mdc_status e;
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q)) != MDC_OK) return e;
+    lsqr_after_fwd(S, q);
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q)) != MDC_OK) return e;
+    lsqr_after_adj(S, q);
+    return check_launch("lsqr iteration");
+  };
+  if (ld.niter >= 1 && (s = iteration(st)) != MDC_OK) return s;  // eager: every kernel variant initialised
+  if (ld.niter < 2) return MDC_OK;
+  const char* g = getenv("MDC_LSQR_GRAPH");
+  const bool use_graph = !op->prof && !(g && g[0] == '0');
+  if (!use_graph) {
+    for (int it = 2; it <= ld.niter; ++it)
+      if ((s = iteration(st)) != MDC_OK) return s;
+    return MDC_OK;
   }
+  // Capture one iteration (identical launches every time: the iteration counter lives on the
+  // device) on the op's private stream, then replay it on the caller's stream.
+  const LsqrGraphKey key{kind, ld.nv, ld.onset, work, x, hist, b};
+  if (!op->lsqr_exec || !(op->lsqr_key == key)) {
+    if (op->lsqr_exec) {
+      hipGraphExecDestroy(op->lsqr_exec);
+      op->lsqr_exec = nullptr;
+    }
+    if (!op->cap_stream && hipStreamCreate(&op->cap_stream) != hipSuccess)
+      return fail(MDC_EDEVICE, "creating the capture stream failed");
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(MDC_EDEVICE, "hipStreamBeginCapture failed");
+    const mdc_status cs = iteration(op->cap_stream);
+    const hipError_t ce = hipStreamEndCapture(op->cap_stream, &graph);
+    if (cs != MDC_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return cs;
+    }
+    if (ce != hipSuccess || !graph) return fail(MDC_EDEVICE, "hipStreamEndCapture failed");
+    const hipError_t ie = hipGraphInstantiate(&op->lsqr_exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      op->lsqr_exec = nullptr;
+      return fail(MDC_EDEVICE, "hipGraphInstantiate failed");
+    }
+    op->lsqr_key = key;
+  }
+  for (int it = 2; it <= ld.niter; ++it)
+    if (hipGraphLaunch(op->lsqr_exec, st) != hipSuccess) return fail(MDC_EDEVICE, "hipGraphLaunch failed");
   return MDC_OK;
 }
 

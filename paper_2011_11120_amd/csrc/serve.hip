@@ -254,7 +254,7 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
         r->phase = r->niter > 0 ? kIterF : kDone;
       } else {
         r->it += 1;
-        lsqr_after_adj(r->S, r->it, st);
+        lsqr_after_adj(r->S, st);
         r->phase = r->it >= r->niter ? kDone : kIterF;
       }
     }

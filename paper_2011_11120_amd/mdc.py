@@ -362,16 +362,20 @@ class MdcOp:
         mch_data(self.handle, onset, nv, fd, d[0], d[1])
         return d
 
-    def lsqr(self, b, niter, kind=MDC_OP_MDC, nv=1, onset=None, hist=True):
+    def lsqr(self, b, niter, kind=MDC_OP_MDC, nv=1, onset=None, hist=True, out=None):
+        """LSQR on the device; out=(x, hist) reuses result buffers (and the captured iteration graph)."""
         ld = lsqr_desc(kind, nv, niter, None if onset is None else onset.data_ptr())
         need = lsqr_query_sizes(self.handle, ld)
         if self._lsqr_work is None or self._lsqr_work.numel() < need:
             self._lsqr_work = torch.empty(need, dtype=torch.uint8, device=b.device)
-        if kind == MDC_OP_MARCHENKO:
-            x = torch.empty((2, self.nt, self.nr, nv), dtype=torch.float32, device=b.device)
+        if out is not None:
+            x, h = out
         else:
-            x = torch.empty((self.nt, self.nr, nv), dtype=torch.float32, device=b.device)
-        h = torch.empty(niter + 1, dtype=torch.float64, device=b.device) if hist else None
+            if kind == MDC_OP_MARCHENKO:
+                x = torch.empty((2, self.nt, self.nr, nv), dtype=torch.float32, device=b.device)
+            else:
+                x = torch.empty((self.nt, self.nr, nv), dtype=torch.float32, device=b.device)
+            h = torch.empty(niter + 1, dtype=torch.float64, device=b.device) if hist else None
         lsqr_solve(self.handle, ld, b, x, h, self._lsqr_work)
         return x, h
 

@@ -107,3 +107,29 @@ def test_lsqr_zero_kernel_returns_data(mdcmod):
     x, hist = op.lsqr(dev(b), 3, kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=dev(onset, torch.int32))
     assert relmax(host(x), b) < 1e-6
     assert host(hist)[-1] < 1e-5 * host(hist)[0]
+
+
+def test_lsqr_graph_replays_match_eager(mdcmod, monkeypatch):
+    """Iterations 2..niter replay one captured graph; every replay equals the eager run bitwise."""
+    nt, nfmax, nx, nv, niter = 64, 25, 5, 2, 9
+    K, onset = marchenko_case(nt, nfmax, nx, nv, seed=7)
+    n = nx * nx
+    op = op_for(mdcmod, K, nt, 2 * nv)
+    on = dev(onset, torch.int32)
+    fd = synth.ricker_spikes(nt, n, nv)
+    d0, d1 = omc.data(K, onset, fd)
+    b = dev(np.stack([d0, d1]))
+    monkeypatch.setenv("MDC_LSQR_GRAPH", "0")
+    xe, he = op.lsqr(b, niter, kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=on)
+    xe, he = xe.clone(), he.clone()
+    monkeypatch.setenv("MDC_LSQR_GRAPH", "1")
+    xg = torch.empty_like(xe)
+    hg = torch.empty_like(he)
+    other = dev(synth.gaussian((nt, n, nv), seed=9))
+    for rep in range(3):
+        xg.zero_()
+        op.lsqr(b, niter, kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=on, out=(xg, hg))
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe) and torch.equal(hg, he), f"replay {rep}"
+        op.forward(other)  # eager work between replays
+        torch.cuda.synchronize()
