@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10, help="c5: requests per run")
     ap.add_argument("--skip", type=int, default=2, help="c5: first completions left out of the latency stats")
     ap.add_argument("--c5-precs", default="fp32,fp16s", help="c5: kernel formats to serve, in order")
+    ap.add_argument("--c5-max-cols", type=int, default=384, help="c5: column budget (2 per focusing point)")
     ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2"], default="fp32",
                     help="kernel storage format for the c3/c4 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -222,6 +223,8 @@ def bench_c3(args):
     n, nv = spec.n, 64
     op = mdc.MdcOp(spec.nt, spec.nfmax, n, n, max_cols=nv, prec=args.prec)
     op.synth_kernel(spec)
+    mdc.mdc_autotune(op.handle)
+    tune = mdc.mdc_tune_table(op.handle)
     x = torch.as_tensor(synth.ricker_spikes(spec.nt, n, nv, dt=spec.dt), dtype=torch.float32).cuda()
     y = torch.as_tensor(synth.gaussian((spec.nt, n, nv)), dtype=torch.float32).cuda()
     yo, xo = torch.empty_like(x), torch.empty_like(y)
@@ -259,6 +262,7 @@ def bench_c3(args):
                 "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "mfma_bf16_TFLOPs": round(nprod * tf, 1), "mfma_bf16_frac": round(nprod * tf / 2500.0, 4)}
     out = {"workload": "MDC GEMM nt=1024 nfmax=300 ns=nr=3600 nv=64, fwd+adj per step", "prec": args.prec,
+           "tuning_table_ncols_fwd_adj": tune,
            "ms_per_step": round(ms_step, 3), "product_ms": round(prod_ms, 3),
            "complex_TFLOPs": round(tf, 2), "roofline": roof,
            "hbm_GBs_product": round(kbytes / (prod_ms * 1e-3) / 1e9, 1),
@@ -278,21 +282,26 @@ def bench_c4(args, niter=30):
         case = workloads.marchenko_case(d=d, kappa_value=workloads.kappa("c4"))
         op = mdc.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv, prec=args.prec)
         op.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
+        mdc.mdc_autotune(op.handle)
         on = torch.as_tensor(case.onset, dtype=torch.int32).cuda()
         fd = torch.as_tensor(case.fd, dtype=torch.float32).cuda()
         dg = op.marchenko_data(on, fd)
-        op.lsqr(dg, 2, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on)  # warm-up (allocates the work buffer)
+        x = torch.empty((2, case.spec.nt, case.n, case.nv), dtype=torch.float32, device="cuda")
+        hist = torch.empty(niter + 1, dtype=torch.float64, device="cuda")
+        op.lsqr(dg, niter, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on, out=(x, hist))  # warm-up + graph capture
         torch.cuda.synchronize()
-        mdc.mdc_profile_read(op.handle)
-        mdc.mdc_profile(op.handle, True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         times = []
-        for _ in range(max(1, args.steps)):
+        for _ in range(max(1, args.steps)):  # timed solves: iterations replay the captured graph
             ev0.record()
-            x, hist = op.lsqr(dg, niter, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+            op.lsqr(dg, niter, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on, out=(x, hist))
             ev1.record()
             torch.cuda.synchronize()
             times.append(ev0.elapsed_time(ev1) / 1e3)
+        mdc.mdc_profile_read(op.handle)
+        mdc.mdc_profile(op.handle, True)  # one more solve with per-stage events (eager, no graph)
+        op.lsqr(dg, niter, kind=mdc.MDC_OP_MARCHENKO, nv=case.nv, onset=on, out=(x, hist))
+        torch.cuda.synchronize()
         mdc.mdc_profile(op.handle, False)
         ms_stage, cnt = mdc.mdc_profile_read(op.handle)
         h = hist.cpu().numpy()
@@ -373,8 +382,9 @@ def bench_c5(args):
     results, sols = {}, {}
     rate = None
     for prec in args.c5_precs.split(","):
-        op = mdc.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, max_cols=256, prec=prec)
+        op = mdc.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, max_cols=args.c5_max_cols, prec=prec)
         op.synth_kernel(spec)
+        mdc.mdc_autotune(op.handle)
         torch.cuda.synchronize()
         free = torch.cuda.mem_get_info()[0]
         out_bytes = 6 * 2 * spec.nt * spec.n * 64 * 4  # room for the outputs of 6 outstanding requests

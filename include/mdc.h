@@ -161,6 +161,20 @@ mdc_status mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float
 mdc_status mdc_profile(mdc_op* op, int enable);
 mdc_status mdc_profile_read(mdc_op* op, double ms[4], int counts[4]);
 
+/* Autotuner of the per-frequency product (the batch matrix multiplication of
+ * Eq.4).  For column counts 1, 2, 3, 4, 6, 8, 12, ... up to max_cols and both
+ * directions it times each kernel family on this op's resident kernel -- the
+ * streaming kernels (family 0), the matrix-core kernels with 64-column tiles
+ * (family 1) and, for complex64 storage, 32-column tiles (family 2) -- and keeps the
+ * fastest per width; later applies of N columns use the entry of the smallest tuned
+ * width >= N.  With cache_path non-NULL, a JSON line per (arch, format, shape) is
+ * read if present (*measured = 0) or appended after measuring (*measured = 1).
+ * Synchronises the stream; overwrites the op's workspace.  Without tuning, up to 8
+ * columns use family 0 and wider products family 1. */
+mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* measured);
+/* The tuning table: count entries; arrays of at least `cap` ints (or NULL). */
+mdc_status mdc_tune_table(const mdc_op* op, int cap, int* count, int* ncols, int* fwd_family, int* adj_family);
+
 mdc_status mdc_destroy(mdc_op* op);
 
 /* ----------------------------------------------------------------- LSQR ----

@@ -50,22 +50,64 @@ size_t store_bytes(const mdc_desc& d) {
   return 0;
 }
 
-// Streaming (GEMV-family) kernels up to kGemvMaxCols columns, matrix cores beyond.
-// MDC_PRODUCT=gemv|gemm in the environment forces one family (for tests).
+// Product families: the streaming kernels, and the matrix-core kernels with 64- or 32-column
+// tiles (FP32) or the split-bf16 kernel (16-bit formats).
+enum Family { kFamGemv = 0, kFamGemm64 = 1, kFamGemm32 = 2 };
+// Default crossover without tuning: streaming kernels up to 8 columns.
 static constexpr int kGemvMaxCols = 8;
 
-mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* kscale, int adjoint,
-                          const float2* in, float2* out, int ncols, hipStream_t st) {
-  bool use_gemm = ncols > kGemvMaxCols;
-  if (const char* e = getenv("MDC_PRODUCT")) {
-    if (!strcmp(e, "gemv")) use_gemm = false;
-    else if (!strcmp(e, "gemm")) use_gemm = true;
-  }
+static mdc_status run_family(const mdc_op* op, int fam, int adjoint, const float2* in, float2* out, int ncols,
+                             hipStream_t st) {
+  const mdc_desc& d = op->d;
   const int ldk = kernel_ld(d.nr);
-  if (!use_gemm) return gemv_launch(d, kstore, kscale, ldk, adjoint, in, out, ncols, st);
+  if (fam == kFamGemv) return gemv_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, st);
   if (d.prec == MDC_FP32)
-    return gemm_launch(d, static_cast<const float2*>(kstore), ldk, adjoint, in, out, ncols, st);
-  return gemm16_launch(d, kstore, kscale, ldk, adjoint, in, out, ncols, st);
+    return gemm_launch(d, static_cast<const float2*>(op->kstore), ldk, adjoint, in, out, ncols, st,
+                       fam == kFamGemm32 ? 32 : 64);
+  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, st);
+}
+
+int choose_family(const mdc_op* op, int adjoint, int ncols) {
+  if (const char* e = getenv("MDC_PRODUCT")) {  // forced family (tests)
+    if (!strcmp(e, "gemv")) return kFamGemv;
+    if (!strcmp(e, "gemm")) return kFamGemm64;
+    if (!strcmp(e, "gemm32")) return op->d.prec == MDC_FP32 ? kFamGemm32 : kFamGemm64;
+  }
+  const auto& ns = op->tune_ncols;
+  if (!ns.empty()) {
+    size_t i = 0;
+    while (i + 1 < ns.size() && ns[i] < ncols) ++i;  // smallest tuned width >= ncols (else the widest)
+    return op->tune_family[adjoint ? 1 : 0][i];
+  }
+  return ncols > kGemvMaxCols ? kFamGemm64 : kFamGemv;
+}
+
+mdc_status product_launch(const mdc_op* op, int adjoint, const float2* in, float2* out, int ncols, hipStream_t st) {
+  return run_family(op, choose_family(op, adjoint, ncols), adjoint, in, out, ncols, st);
+}
+
+// Time one family at one width on the op's own kernel (ms per launch, best of 3).
+float time_family(mdc_op* op, int fam, int adjoint, int ncols, hipStream_t st) {
+  float2* in = adjoint ? op->specS : op->specR;
+  float2* out = adjoint ? op->specR : op->specS;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  float best = 3.0e38f;
+  if (run_family(op, fam, adjoint, in, out, ncols, st) == MDC_OK) {  // warm-up
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(a, st);
+      run_family(op, fam, adjoint, in, out, ncols, st);
+      hipEventRecord(b, st);
+      hipEventSynchronize(b);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, a, b);
+      best = ms < best ? ms : best;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return best;
 }
 
 }  // namespace mdc
@@ -164,7 +206,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   }
   {
     Stage t(op, adjoint ? 2 : 1, st);
-    if ((s = product_launch(d, op->kstore, op->fscale, adjoint, spec_in, spec_out, nv, st)) != MDC_OK) return s;
+    if ((s = product_launch(op, adjoint, spec_in, spec_out, nv, st)) != MDC_OK) return s;
   }
   {
     Stage t(op, 3, st);
@@ -201,7 +243,7 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
   }
   {
     Stage t(op, adjoint ? 2 : 1, st);
-    if ((s = product_launch(d, op->kstore, op->fscale, adjoint, spec_in, spec_out, N, st)) != MDC_OK) return s;
+    if ((s = product_launch(op, adjoint, spec_in, spec_out, N, st)) != MDC_OK) return s;
   }
   {
     Stage t(op, 3, st);
@@ -240,7 +282,7 @@ mdc_status apply_mch_data(mdc_op* op, const int* onset, int nv, const float* fd,
   }
   {
     Stage t(op, 1, st);
-    if ((s = product_launch(d, op->kstore, op->fscale, 0, op->specR, op->specS, nv, st)) != MDC_OK) return s;
+    if ((s = product_launch(op, 0, op->specR, op->specS, nv, st)) != MDC_OK) return s;
   }
   {
     Stage t(op, 3, st);
@@ -456,6 +498,112 @@ mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, c
 mdc_status mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float* d0, float* d1, void* stream) {
   if (!op) return fail(MDC_EINVAL, "op is NULL");
   return apply_mch_data(op, onset, nv, fd, d0, d1, static_cast<hipStream_t>(stream));
+}
+
+static void tune_key(const mdc_op* op, char* buf, size_t n) {
+  const mdc_desc& d = op->d;
+  snprintf(buf, n, "gfx950 prec=%d nt=%d nfmax=%d ns=%d nr=%d max_cols=%d", (int)d.prec, d.nt, d.nfmax, d.ns, d.nr,
+           d.max_cols);
+}
+
+// Parse `"name": [a, b, ...]` from a JSON line into v.
+static bool parse_array(const char* line, const char* name, std::vector<int>& v) {
+  char pat[64];
+  snprintf(pat, sizeof pat, "\"%s\": [", name);
+  const char* p = strstr(line, pat);
+  if (!p) return false;
+  p += strlen(pat);
+  v.clear();
+  while (*p && *p != ']') {
+    char* end = nullptr;
+    const long x = strtol(p, &end, 10);
+    if (end == p) return false;
+    v.push_back((int)x);
+    p = end;
+    while (*p == ',' || *p == ' ') ++p;
+  }
+  return *p == ']';
+}
+
+mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* measured) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  char key[160];
+  tune_key(op, key, sizeof key);
+  if (measured) *measured = 0;
+  if (cache_path) {
+    if (FILE* fh = fopen(cache_path, "r")) {
+      char line[8192];
+      char kpat[200];
+      snprintf(kpat, sizeof kpat, "\"key\": \"%s\"", key);
+      bool found = false;
+      while (fgets(line, sizeof line, fh)) {
+        if (!strstr(line, kpat)) continue;
+        std::vector<int> nc, fw, ad;
+        if (parse_array(line, "ncols", nc) && parse_array(line, "fwd", fw) && parse_array(line, "adj", ad) &&
+            !nc.empty() && nc.size() == fw.size() && nc.size() == ad.size()) {
+          op->tune_ncols = nc;
+          op->tune_family[0] = fw;
+          op->tune_family[1] = ad;
+          found = true;
+        }
+      }
+      fclose(fh);
+      if (found) return MDC_OK;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+  std::vector<int> nc;
+  for (int c : cand)
+    if (c <= op->d.max_cols) nc.push_back(c);
+  if (nc.empty() || nc.back() != op->d.max_cols) nc.push_back(op->d.max_cols);
+  std::vector<int> fams = {kFamGemv, kFamGemm64};
+  if (op->d.prec == MDC_FP32) fams.push_back(kFamGemm32);
+  std::vector<int> best[2];
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int n : nc) {
+      int bf = -1;
+      float bt = 3.0e38f;
+      for (int fam : fams) {
+        if (fam == kFamGemv && n > 32) continue;  // streaming kernels re-read the kernel every 8 columns
+        if (fam == kFamGemm32 && n > 64) continue;
+        const float t = time_family(op, fam, dir, n, st);
+        if (t < bt) { bt = t; bf = fam; }
+      }
+      if (bf < 0) return fail(MDC_EDEVICE, "autotune: no product family ran");
+      best[dir].push_back(bf);
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return fail(MDC_EDEVICE, "autotune: a timing launch failed");
+  op->tune_ncols = nc;
+  op->tune_family[0] = best[0];
+  op->tune_family[1] = best[1];
+  if (measured) *measured = 1;
+  if (cache_path) {
+    if (FILE* fh = fopen(cache_path, "a")) {
+      fprintf(fh, "{\"key\": \"%s\", \"ncols\": [", key);
+      for (size_t i = 0; i < nc.size(); ++i) fprintf(fh, "%s%d", i ? ", " : "", nc[i]);
+      fprintf(fh, "], \"fwd\": [");
+      for (size_t i = 0; i < nc.size(); ++i) fprintf(fh, "%s%d", i ? ", " : "", best[0][i]);
+      fprintf(fh, "], \"adj\": [");
+      for (size_t i = 0; i < nc.size(); ++i) fprintf(fh, "%s%d", i ? ", " : "", best[1][i]);
+      fprintf(fh, "]}\n");
+      fclose(fh);
+    }
+  }
+  return MDC_OK;
+}
+
+mdc_status mdc_tune_table(const mdc_op* op, int cap, int* count, int* ncols, int* fwd_family, int* adj_family) {
+  if (!op || !count) return fail(MDC_EINVAL, "NULL argument");
+  *count = (int)op->tune_ncols.size();
+  for (int i = 0; i < *count && i < cap; ++i) {
+    if (ncols) ncols[i] = op->tune_ncols[i];
+    if (fwd_family) fwd_family[i] = op->tune_family[0][i];
+    if (adj_family) adj_family[i] = op->tune_family[1][i];
+  }
+  return MDC_OK;
 }
 
 mdc_status mdc_profile(mdc_op* op, int enable) {

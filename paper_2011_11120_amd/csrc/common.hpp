@@ -35,6 +35,9 @@ struct mdc_op {
   struct Ev { int stage; hipEvent_t a, b; };
   std::vector<Ev> evs;
   std::vector<hipEvent_t> pool;
+  // product family per column bucket and direction (filled by mdc_autotune)
+  std::vector<int> tune_ncols;
+  std::vector<int> tune_family[2];
   // LSQR iteration graph (captured on cap_stream, replayed on the caller's stream)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t lsqr_exec = nullptr;
@@ -92,9 +95,9 @@ mdc_status irfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int 
                         const float2* spec, hipStream_t st);
 
 // Kernel product over all frequencies: forward Y_f = K_f X_f (ns x nr times nr x ncols),
-// adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].
-mdc_status product_launch(const mdc_desc& d, const void* kstore, const float* kscale, int adjoint,
-                          const float2* in, float2* out, int ncols, hipStream_t st);
+// adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].  The kernel family comes from the
+// op's tuning table (mdc_autotune), else from the default crossover.
+mdc_status product_launch(const mdc_op* op, int adjoint, const float2* in, float2* out, int ncols, hipStream_t st);
 
 // Device state of one LSQR solve (all pointers are device memory).
 struct LsqrState {

@@ -15,8 +15,8 @@
 //
 // One MFMA k-step of depth 4 consumes two complex columns of the kernel.  The
 // B fragments are formed from the complex spectra held in LDS at read time.
-// Tiles: a 256-thread workgroup computes 128 output rows x 64 complex columns
-// (four waves of 64 x 64 real outputs, 16 MFMA blocks each), stepping through
+// Tiles: a 256-thread workgroup computes 128 output rows x BN complex columns
+// (BN = 64 or 32; four waves of 64 x BN real outputs), stepping through
 // the reduction 16 complex columns at a time with double-buffered LDS and a
 // register prefetch of the next slab.  Workgroups are numbered so that all
 // tiles of one frequency run on the same XCD (hardware deals workgroups
@@ -31,18 +31,20 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int BM = 128;        // output rows per workgroup
-constexpr int BN = 64;         // complex output columns per workgroup
 constexpr int BK = 16;         // complex reduction columns per slab
 constexpr int A_FWD_LD = 36;   // floats per A row (forward): 2*BK + 4 pad
 constexpr int A_ADJ_LD = 288;  // floats per A row (adjoint): 2*BM + 32 pad
 constexpr int A_FLOATS = 4608; // BM*A_FWD_LD == BK*A_ADJ_LD
-constexpr int B_LD = BN + 2;   // complex per B row
 
-template <bool ADJ>
+// BN complex output columns per workgroup (64 or 32; the autotuner picks).
+template <bool ADJ, int BN>
 __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __restrict__ K, int ns, int nr, int ldk,
                                                                const float2* __restrict__ Bsrc,
                                                                float2* __restrict__ Cdst, int ncols, int tiles_m,
                                                                int tiles_n, int nblocks) {
+  constexpr int B_LD = BN + 2;        // complex per B row
+  constexpr int NI = BN / 16;         // 16-real-column MFMA blocks per wave (a wave covers BN real columns)
+  constexpr int B_LOADS = BK * BN / kThreads;
   __shared__ __attribute__((aligned(16))) float As[2][A_FLOATS];
   __shared__ __attribute__((aligned(16))) float2 Bs[2][BK * B_LD];
 
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
   const int li = lane & 15, lk = lane >> 4;
 
   float4 pa[4];
-  float2 pb[4];
+  float2 pb[B_LOADS];
   auto load_slab = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -86,9 +88,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
       pa[q] = v;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B_LOADS; ++q) {
       const int idx = tid + kThreads * q;
-      const int rr = idx >> 6, c = idx & 63;
+      const int rr = idx / BN, c = idx % BN;
       const int kk = k0 + rr, v = n0 + c;
       pb[q] = (kk < KD && v < ncols) ? Bf[(size_t)kk * ncols + v] : make_float2(0.f, 0.f);
     }
@@ -103,17 +105,17 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
       *reinterpret_cast<float4*>(&As[buf][off]) = pa[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B_LOADS; ++q) {
       const int idx = tid + kThreads * q;
-      Bs[buf][(idx >> 6) * B_LD + (idx & 63)] = pb[q];
+      Bs[buf][(idx / BN) * B_LD + (idx % BN)] = pb[q];
     }
   };
 
-  f4v acc[4][4];
+  f4v acc[4][NI];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NI; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
   const int nslabs = (KD + BK - 1) / BK;
   load_slab(0);
@@ -128,15 +130,15 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
     for (int ks = 0; ks < BK / 2; ++ks) {
       const int cc = 2 * ks + (lk >> 1);  // complex reduction index within the slab
       const int part = lk & 1;
-      float a[4], bv[4];
+      float a[4], bv[NI];
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) {
         const int row = wm * 64 + mi * 16 + li;
         a[mi] = ADJ ? A[cc * A_ADJ_LD + 2 * row + part] : A[row * A_FWD_LD + 2 * cc + part];
       }
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        const int n = wn * 64 + ni * 16 + li;  // real column within the tile
+      for (int ni = 0; ni < NI; ++ni) {
+        const int n = wn * (BN) + ni * 16 + li;  // real column within the tile
         const float2 z = Bl[cc * B_LD + (n >> 1)];
         const int jj = n & 1;
         if (!ADJ) bv[ni] = part == 0 ? (jj == 0 ? z.x : z.y) : (jj == 0 ? -z.y : z.x);
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
+        for (int ni = 0; ni < NI; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], bv[ni], acc[mi][ni], 0, 0, 0);
     }
     if (sl + 1 < nslabs) store_slab(buf ^ 1);
@@ -156,8 +158,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
-      const int n = 2 * n0 + wn * 64 + ni * 16 + li;  // real output column
+    for (int ni = 0; ni < NI; ++ni) {
+      const int n = 2 * n0 + wn * (BN) + ni * 16 + li;  // real output column
       const int v = n >> 1;
       if (v >= ncols) continue;
 #pragma unroll
@@ -168,10 +170,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
     }
 }
 
-}  // namespace
-
-mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
-                       int ncols, hipStream_t st) {
+template <int BN>
+mdc_status gemm_bn(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out, int ncols,
+                   hipStream_t st) {
   const int M = adjoint ? d.nr : d.ns;
   const int tiles_m = (M + BM - 1) / BM;
   const int tiles_n = (ncols + BN - 1) / BN;
@@ -179,12 +180,21 @@ mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint,
   if (nb > 0x7fffffffL) return fail(MDC_ENOTSUP, "too many GEMM tiles");
   const int nblocks = (int)nb;
   if (adjoint)
-    hipLaunchKernelGGL(gemm_f32_kernel<true>, dim3(nblocks), dim3(kThreads), 0, st, K, d.ns, d.nr, ldk, in, out,
+    hipLaunchKernelGGL((gemm_f32_kernel<true, BN>), dim3(nblocks), dim3(kThreads), 0, st, K, d.ns, d.nr, ldk, in, out,
                        ncols, tiles_m, tiles_n, nblocks);
   else
-    hipLaunchKernelGGL(gemm_f32_kernel<false>, dim3(nblocks), dim3(kThreads), 0, st, K, d.ns, d.nr, ldk, in, out,
-                       ncols, tiles_m, tiles_n, nblocks);
+    hipLaunchKernelGGL((gemm_f32_kernel<false, BN>), dim3(nblocks), dim3(kThreads), 0, st, K, d.ns, d.nr, ldk, in,
+                       out, ncols, tiles_m, tiles_n, nblocks);
   return check_launch("gemm_f32_kernel");
+}
+
+}  // namespace
+
+// bn: 64 or 32 complex columns per workgroup.
+mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
+                       int ncols, hipStream_t st, int bn) {
+  if (bn == 32) return gemm_bn<32>(d, K, ldk, adjoint, in, out, ncols, st);
+  return gemm_bn<64>(d, K, ldk, adjoint, in, out, ncols, st);
 }
 
 }  // namespace mdc

@@ -226,7 +226,7 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
     }
   }
-  if ((s = product_launch(d, op->kstore, op->fscale, fwd ? 0 : 1, spec_in, spec_out, N, st)) != MDC_OK) return s;
+  if ((s = product_launch(op, fwd ? 0 : 1, spec_in, spec_out, N, st)) != MDC_OK) return s;
   for (Request* r : part) {
     const size_t half = (size_t)d.nt * n * r->nv;
     const float dsc = (float)r->decim;

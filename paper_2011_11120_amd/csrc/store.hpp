@@ -102,6 +102,6 @@ mdc_status fp16_scales_launch(float* fscale, int nfmax, hipStream_t st);
 mdc_status gemm16_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint,
                          const float2* in, float2* out, int ncols, hipStream_t st);
 mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
-                       int ncols, hipStream_t st);
+                       int ncols, hipStream_t st, int bn);
 
 }  // namespace mdc

@@ -78,6 +78,9 @@ def _load():
         "mdc_profile": (st, [vp, i]),
         "mdc_profile_read": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         "mdc_destroy": (st, [vp]),
+        "mdc_autotune": (st, [vp, C.c_char_p, vp, C.POINTER(C.c_int)]),
+        "mdc_tune_table": (st, [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int)]),
         "lsqr_query_sizes": (st, [vp, C.POINTER(lsqr_desc), C.POINTER(C.c_size_t)]),
         "lsqr_solve": (st, [vp, C.POINTER(lsqr_desc), vp, vp, vp, vp, C.c_size_t, vp]),
         "serve_request_bytes": (st, [vp, i, C.POINTER(C.c_size_t)]),
@@ -100,7 +103,8 @@ def _load():
 _lib = _load()
 EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", "mdc_synth_kernel",
            "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mch_forward", "mch_adjoint", "mch_data",
-           "mdc_profile", "mdc_profile_read", "mdc_destroy", "lsqr_query_sizes", "lsqr_solve",
+           "mdc_profile", "mdc_profile_read", "mdc_destroy", "mdc_autotune", "mdc_tune_table",
+           "lsqr_query_sizes", "lsqr_solve",
            "serve_request_bytes", "serve_create", "serve_submit", "serve_poll", "serve_cancel", "serve_drain",
            "serve_stats", "serve_destroy")
 
@@ -187,6 +191,23 @@ def mdc_profile_read(h):
     cnt = (C.c_int * 4)()
     _check(_lib.mdc_profile_read(h, ms, cnt))
     return list(ms), list(cnt)
+
+
+def mdc_autotune(h, cache_path=None, stream=None) -> bool:
+    """Returns True when the table was measured, False when it came from the cache."""
+    m = C.c_int(0)
+    _check(_lib.mdc_autotune(h, None if cache_path is None else str(cache_path).encode(), _stream(stream),
+                             C.byref(m)))
+    return bool(m.value)
+
+
+def mdc_tune_table(h):
+    cnt = C.c_int(0)
+    _check(_lib.mdc_tune_table(h, 0, C.byref(cnt), None, None, None))
+    n = cnt.value
+    a, b, c = (C.c_int * max(n, 1))(), (C.c_int * max(n, 1))(), (C.c_int * max(n, 1))()
+    _check(_lib.mdc_tune_table(h, n, C.byref(cnt), a, b, c))
+    return [(a[i], b[i], c[i]) for i in range(n)]
 
 
 def mdc_destroy(h):

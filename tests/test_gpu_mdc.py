@@ -302,3 +302,37 @@ def test_c3_full_size_sampled(mdcmod):
     xsub = xg[:, idx][:, :, vs].cpu().numpy().astype(np.float64)
     assert relmax(xsub, xref) < TOL
     op.close()
+
+
+@pytest.mark.parametrize("nv", [9, 33, 64, 65])
+def test_gemm32_tiles_match_oracle(mdcmod, monkeypatch, nv):
+    monkeypatch.setenv("MDC_PRODUCT", "gemm32")
+    nt, nfmax, ns, nr = 128, 40, 150, 98
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=31)
+    op = make_op(mdcmod, K, nt, max_cols=nv)
+    x = synth.gaussian((nt, nr, nv), seed=5)
+    y = synth.gaussian((nt, ns, nv), seed=6)
+    assert relmax(host(op.forward(dev(x))), om.mdc_forward(K, x)) < TOL
+    assert relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y)) < TOL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_autotune_table_cache_and_parity(mdcmod, tmp_path, prec):
+    nt, nfmax, n, maxc = 128, 40, 130, 64
+    K = synth.random_complex_kernel(nfmax, n, n, seed=32)
+    op = mdcmod.MdcOp(nt, nfmax, n, n, max_cols=maxc, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    cache = tmp_path / "tune.jsonl"
+    assert mdcmod.mdc_autotune(op.handle, cache) is True
+    table = mdcmod.mdc_tune_table(op.handle)
+    print(f"{prec} tuning table (ncols, fwd family, adj family): {table}", flush=True)
+    assert [t[0] for t in table][-1] == maxc and all(f in (0, 1, 2) for t in table for f in t[1:])
+    op2 = mdcmod.MdcOp(nt, nfmax, n, n, max_cols=maxc, prec=prec)
+    op2.set_kernel(dev(K, torch.complex64))
+    assert mdcmod.mdc_autotune(op2.handle, cache) is False
+    assert mdcmod.mdc_tune_table(op2.handle) == table
+    tol = 1e-5 if prec == "fp32" else 2e-3
+    for nv in (1, 5, 20, 64):
+        x = synth.gaussian((nt, n, nv), seed=nv)
+        assert relmax(host(op.forward(dev(x))), om.mdc_forward(K, x)) < tol
+        assert relmax(host(op.adjoint(dev(x))), om.mdc_adjoint(K, x)) < tol
