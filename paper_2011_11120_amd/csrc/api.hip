@@ -566,7 +566,7 @@ mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* m
       int bf = -1;
       float bt = 3.0e38f;
       for (int fam : fams) {
-        if (fam == kFamGemv && n > 32) continue;  // streaming kernels re-read the kernel every 8 columns
+        if (fam == kFamGemv && n > 16) continue;  // streaming kernels re-read the kernel every 8 columns
         if (fam == kFamGemm32 && n > 64) continue;
         const float t = time_family(op, fam, dir, n, st);
         if (t < bt) { bt = t; bf = fam; }

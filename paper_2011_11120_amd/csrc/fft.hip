@@ -123,8 +123,9 @@ __device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __rest
 
 // ----------------------------------------------------------------- forward ---
 // VEC: Q % 4 == 0 and x 16-byte aligned (four traces per 16-byte load);
-// CONTIG: the spectrum of consecutive traces is contiguous (one segment), so
-// two bins of a trace pair go out as one 16-byte store.
+// CONTIG: the bins of a trace pair (q, q+1), q even, are adjacent and 16-byte
+// aligned in the spectrum (one segment with Q even, or nv, ldc and c0 all even)
+// and go out as one 16-byte store.
 template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
     const float* __restrict__ x, const int* __restrict__ onset, int conj, const float2* __restrict__ tw,
@@ -223,11 +224,11 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
     }
     const int q = q0 + 2 * p;
     if (CONTIG) {
-      // one segment with ldc == nv: spec index k*Q + q; Q even keeps the pair aligned
+      // traces q, q+1 (q even) are adjacent spectral columns (see CONTIG above)
       if (q + 1 < Q) {
-        *reinterpret_cast<float4*>(spec + (size_t)k * Q + q) = make_float4(X[0].x, X[0].y, X[1].x, X[1].y);
-      } else if (q < Q) {
-        spec[(size_t)k * Q + q] = X[0];
+        const int r = q / nv, v = q - r * nv;
+        *reinterpret_cast<float4*>(spec + ((size_t)k * n + r) * ldc + c0 + v) =
+            make_float4(X[0].x, X[0].y, X[1].x, X[1].y);
       }
     } else {
 #pragma unroll
@@ -261,13 +262,12 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   auto bin2 = [&](int k, int q, float2& X0, float2& X1) {
     X0 = X1 = make_float2(0.f, 0.f);
     if (k >= nfmax) return;
-    if (CONTIG) {
+    if (CONTIG) {  // pair of adjacent, 16-byte aligned columns (see the forward split step)
       if (q + 1 < Q) {
-        const float4 v = *reinterpret_cast<const float4*>(spec + (size_t)k * Q + q);
-        X0 = make_float2(v.x, v.y);
-        X1 = make_float2(v.z, v.w);
-      } else if (q < Q) {
-        X0 = spec[(size_t)k * Q + q];
+        const int r = q / nv, v = q - r * nv;
+        const float4 w = *reinterpret_cast<const float4*>(spec + ((size_t)k * n + r) * ldc + c0 + v);
+        X0 = make_float2(w.x, w.y);
+        X1 = make_float2(w.z, w.w);
       }
     } else {
       if (q < Q) X0 = spec[((size_t)k * n + q / nv) * ldc + c0 + q % nv];
@@ -388,7 +388,9 @@ mdc_status rfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const Ff
                    hipStream_t st) {
   const int Q = n * nv;
   const bool vec = (Q % 4 == 0) && aligned(s.in, 16);
-  const bool contig = (ldc == nv) && (Q % 2 == 0) && aligned(spec, 16);
+  // pairs contiguous: one segment (ldc == nv, c0 == 0, Q even), or nv, ldc, c0 all even
+  const bool contig = aligned(spec, 16) && ((ldc == nv && s.c0 == 0 && Q % 2 == 0) ||
+                                            (nv % 2 == 0 && ldc % 2 == 0 && s.c0 % 2 == 0));
   if (vec && contig) return rfft_run<M, CB, true, true>(tw, nfmax, n, nv, ldc, s, spec, st);
   if (vec) return rfft_run<M, CB, true, false>(tw, nfmax, n, nv, ldc, s, spec, st);
   if (contig) return rfft_run<M, CB, false, true>(tw, nfmax, n, nv, ldc, s, spec, st);
@@ -425,7 +427,9 @@ mdc_status irfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const I
                     hipStream_t st) {
   const int Q = n * nv;
   const bool vec = (Q % 4 == 0) && aligned(s.out, 16) && (s.ident == nullptr || aligned(s.ident, 16));
-  const bool contig = (ldc == nv) && (Q % 2 == 0) && aligned(spec, 16);
+  // pairs contiguous: one segment (ldc == nv, c0 == 0, Q even), or nv, ldc, c0 all even
+  const bool contig = aligned(spec, 16) && ((ldc == nv && s.c0 == 0 && Q % 2 == 0) ||
+                                            (nv % 2 == 0 && ldc % 2 == 0 && s.c0 % 2 == 0));
   if (vec && contig) return irfft_run<M, CB, true, true>(tw, nfmax, n, nv, ldc, s, spec, st);
   if (vec) return irfft_run<M, CB, true, false>(tw, nfmax, n, nv, ldc, s, spec, st);
   if (contig) return irfft_run<M, CB, false, true>(tw, nfmax, n, nv, ldc, s, spec, st);
