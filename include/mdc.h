@@ -126,6 +126,16 @@ typedef struct {
 } mdc_synth_desc;
 mdc_status mdc_synth_kernel(mdc_op* op, const mdc_synth_desc* sd, void* stream);
 
+/* Kernel from time-domain traces g[t][s][r] (device float, nt x ns x nr): each trace is
+ * transformed with the library's real FFT, K[f][s][r] = scale * col_weight[r] *
+ * sum_t g[t][s][r] exp(-2 pi i f t / nt) for f < nfmax (conjugated when conj != 0, which
+ * turns traces of g(-t) into the kernel of g), then stored in the op's format: the
+ * time-to-frequency preprocessing of the kernel (batch-matmul section), with
+ * scale = dt * dA for Eq.1's integral.  temp: device scratch of 8*nfmax*ns*nr bytes,
+ * or NULL for complex64 storage with nr a multiple of 4 (transformed in place). */
+mdc_status mdc_set_kernel_time(mdc_op* op, const float* g, int conj, double scale, const float* col_weight,
+                               void* temp, size_t temp_bytes, void* stream);
+
 /* Read back element (f, s, r) of the resident kernel as complex64 (host
  * pointers re/im; synchronises the stream).  For tests of the loaders. */
 mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, float* re, float* im);
@@ -152,6 +162,21 @@ mdc_status mch_adjoint(mdc_op* op, const int* onset, int nv, const float* in0, c
 /* Right-hand side of Eq.5: d0 = Theta R fd, d1 = 0, with fd [nt][n][nv] the
  * direct (initial) focusing function; nv <= max_cols. */
 mdc_status mch_data(mdc_op* op, const int* onset, int nv, const float* fd, float* d0, float* d1, void* stream);
+
+/* Green's functions of Eq.6 from the focusing functions (square op, 2*nv <= max_cols):
+ *   g- = R f+ - f-,   g+* = f+ - R* f-,   f+ = fd + fm
+ * (the sign convention of Eq.6: [-g-; g+*] = [[I, -R], [-R*, I]] [f-; f+]).  All arrays
+ * are device [nt][n][nv]; gminus and gplus_conj must not alias the inputs. */
+mdc_status mch_greens(mdc_op* op, int nv, const float* fminus, const float* fd, const float* fm, float* gminus,
+                      float* gplus_conj, void* stream);
+
+/* Forward-only (Neumann) scheme for Eq.5: f = sum_{k<nterms} B^k d with B = I - M,
+ * i.e. B [a0; a1] = [Theta R a1; Theta R* a0]; converges when rho(B) < 1 (Applications:
+ * Neumann vs gradient solvers).  d, f: device [2][nt][n][nv]; work from
+ * mch_neumann_query. */
+mdc_status mch_neumann_query(const mdc_op* op, int nv, size_t* work_bytes);
+mdc_status mch_neumann(mdc_op* op, const int* onset, int nv, const float* d, float* f, int nterms, void* work,
+                       size_t work_bytes, void* stream);
 
 /* Per-stage timing with HIP events on the apply stream (for measurement).
  * enable != 0 starts recording; mdc_profile_read synchronises and returns the
@@ -202,6 +227,13 @@ mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_
  * norm estimate) after each iteration, or NULL; work: device workspace. */
 mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist,
                       void* work, size_t work_bytes, void* stream);
+
+/* CGLS, the solver the paper runs (Applications: 10 iterations): conjugate gradients on
+ * the normal equations, x0 = 0, fixed niter, same operators, layouts and workspace size
+ * (lsqr_query_sizes) as lsqr_solve; hist receives ||b - A x_i|| for i = 0..niter.
+ * FP32 vectors, FP64 scalars on the device. */
+mdc_status cgls_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist, void* work,
+                      size_t work_bytes, void* stream);
 
 /* -------------------------------------------------------------- serving ----
  * A server runs Marchenko LSQR solves (Eq.5) for requests that arrive over

@@ -218,7 +218,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
 
 // Marchenko block operator (Eq.5): one kernel pass with columns [block for R | conj block for R*].
 mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
-                           float* out1, int adjoint, hipStream_t st) {
+                           float* out1, int adjoint, hipStream_t st, int mode = 0) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
   if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
@@ -250,8 +250,10 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     const int* post = adjoint ? nullptr : onset;
     // forward: out0 = in0 - Theta R in1 (cols 0..nv), out1 = in1 - Theta R* in0 (cols nv..2nv, conj)
     // adjoint: out1 = in1 - R^H Theta in0 (cols 0..nv), out0 = in0 - R*^H Theta in1 (cols nv..2nv, conj)
-    IfftSeg a{adjoint ? out1 : out0, adjoint ? in1 : in0, post, 0, 0, -1.0f};
-    IfftSeg b{adjoint ? out0 : out1, adjoint ? in0 : in1, post, 1, nv, -1.0f};
+    // mode 1 (Neumann term B = I - M): no identity blocks, + sign
+    const float sg = mode == 1 ? 1.0f : -1.0f;
+    IfftSeg a{adjoint ? out1 : out0, mode == 1 ? nullptr : (adjoint ? in1 : in0), post, 0, 0, sg};
+    IfftSeg b{adjoint ? out0 : out1, mode == 1 ? nullptr : (adjoint ? in0 : in1), post, 1, nv, sg};
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_out, st)) != MDC_OK) return s;
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_out, st)) != MDC_OK) return s;
   }
@@ -296,7 +298,7 @@ mdc_status apply_mch_data(mdc_op* op, const int* onset, int nv, const float* fd,
 // Scaled conversion of a complex64 kernel [nfmax][ns][nr] into the resident store
 // [nfmax][ns][ldk] (pad columns zero), through one of the storage formats.
 template <typename Store>
-__global__ void load_kernel(const float2* __restrict__ K, Store out, int nfmax, int ns, int nr, int ldk, double scale,
+__global__ void load_kernel(const float2* K, Store out, int nfmax, int ns, int nr, int ldk, double scale,
                             const float* __restrict__ w) {
   const size_t count = (size_t)nfmax * ns * ldk;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
@@ -324,12 +326,81 @@ mdc_status launch_load(mdc_op* op, const float2* K, double scale, const float* w
   return check_launch("load_kernel");
 }
 
+__global__ void add2(float* __restrict__ out, const float* __restrict__ a, const float* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = a[i] + b[i];
+}
+
+__global__ void copy2(float* __restrict__ a, float* __restrict__ b, const float* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float v = src[i];
+    a[i] = v;
+    b[i] = v;
+  }
+}
+
+__global__ void acc_add(float* __restrict__ f, const float* __restrict__ t, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) f[i] += t[i];
+}
+
+// Eq.6: g- = R f+ - f-,  g+* = f+ - R* f-,  f+ = fd + fm (formed in gpc first).
+mdc_status apply_greens(mdc_op* op, int nv, const float* fminus, const float* fd, const float* fm, float* gminus,
+                        float* gpc, hipStream_t st) {
+  const mdc_desc& d = op->d;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if (d.ns != d.nr) return fail(MDC_EINVAL, "Green's functions need ns == nr");
+  if (nv < 1 || 2 * nv > d.max_cols) return fail(MDC_EINVAL, "2*nv=%d outside [2, max_cols=%d]", 2 * nv, d.max_cols);
+  mdc_status s;
+  if ((s = check_vec(fminus, "fminus")) != MDC_OK || (s = check_vec(fd, "fd")) != MDC_OK ||
+      (s = check_vec(fm, "fm")) != MDC_OK || (s = check_vec(gminus, "gminus")) != MDC_OK ||
+      (s = check_vec(gpc, "gplus_conj")) != MDC_OK)
+    return s;
+  const int n = d.ns, N = 2 * nv;
+  hipLaunchKernelGGL(add2, dim3(1024), dim3(256), 0, st, gpc, fd, fm, (size_t)d.nt * n * nv);
+  if ((s = check_launch("add2")) != MDC_OK) return s;
+  FftSeg a{gpc, nullptr, 0, 0};
+  FftSeg b{fminus, nullptr, 1, nv};
+  if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, op->specR, st)) != MDC_OK) return s;
+  if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, op->specR, st)) != MDC_OK) return s;
+  if ((s = product_launch(op, 0, op->specR, op->specS, N, st)) != MDC_OK) return s;
+  IfftSeg ga{gminus, fminus, nullptr, 0, 0, 1.0f, -1.0f};
+  IfftSeg gb{gpc, gpc, nullptr, 1, nv, -1.0f, 1.0f};
+  if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, ga, op->specS, st)) != MDC_OK) return s;
+  return irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, gb, op->specS, st);
+}
+
+// f = sum_{k < nterms} B^k d with B = I - M (forward-only scheme; needs rho(B) < 1).
+mdc_status apply_neumann(mdc_op* op, const int* onset, int nv, const float* dvec, float* f, int nterms, void* work,
+                         size_t work_bytes, hipStream_t st) {
+  const mdc_desc& d = op->d;
+  const size_t blk = (size_t)d.nt * d.ns * nv, vec = 2 * blk;
+  const size_t need = 2 * align_up(vec * 4, 256);
+  if (!work || !aligned(work, 256)) return fail(MDC_EINVAL, "work must be non-NULL and 256-byte aligned");
+  if (work_bytes < need) return fail(MDC_ENOMEM, "work has %zu bytes, %zu needed", work_bytes, need);
+  if (nterms < 1) return fail(MDC_EINVAL, "nterms must be >= 1");
+  mdc_status s;
+  if ((s = check_vec(dvec, "d")) != MDC_OK || (s = check_vec(f, "f")) != MDC_OK) return s;
+  float* t = static_cast<float*>(work);
+  float* t2 = reinterpret_cast<float*>(static_cast<char*>(work) + align_up(vec * 4, 256));
+  hipLaunchKernelGGL(copy2, dim3(1024), dim3(256), 0, st, f, t, dvec, vec);
+  for (int k = 1; k < nterms; ++k) {
+    if ((s = apply_marchenko(op, onset, nv, t, t + blk, t2, t2 + blk, 0, st, 1)) != MDC_OK) return s;
+    hipLaunchKernelGGL(acc_add, dim3(1024), dim3(256), 0, st, f, t2, vec);
+    float* tmp = t;
+    t = t2;
+    t2 = tmp;
+  }
+  return check_launch("neumann");
+}
+
 }  // namespace
 
 namespace mdc {
 mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld);
 size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld);
 mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
+                    void* work, hipStream_t st);
+mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
                     void* work, hipStream_t st);
 
 // One application of the solver's operator (MDC or Marchenko); Marchenko vectors are two
@@ -411,6 +482,47 @@ mdc_status mdc_set_kernel(mdc_op* op, const void* K, double scale, const float* 
   }
   if (s == MDC_OK) op->kernel_ready = true;
   return s;
+}
+
+mdc_status mdc_set_kernel_time(mdc_op* op, const float* g, int conj, double scale, const float* col_weight, void* temp,
+                               size_t temp_bytes, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  const mdc_desc& d = op->d;
+  if (!g || !aligned(g, 4)) return fail(MDC_EINVAL, "g must be non-NULL and 4-byte aligned");
+  const size_t need = (size_t)8 * d.nfmax * d.ns * d.nr;
+  const bool in_place = temp == nullptr;
+  if (in_place && !(d.prec == MDC_FP32 && d.nr % 4 == 0))
+    return fail(MDC_EINVAL, "temp may be NULL only for complex64 storage with nr a multiple of 4");
+  if (!in_place && (!aligned(temp, 256) || temp_bytes < need))
+    return fail(MDC_ENOMEM, "temp needs %zu bytes, 256-byte aligned", need);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* spec = in_place ? static_cast<float2*>(op->kstore) : static_cast<float2*>(temp);
+  // orthogonal FFT of every trace (s, r), then x sqrt(nt): the unnormalised DFT of Eq.2's kernel
+  FftSeg seg{g, nullptr, conj ? 1 : 0, 0};
+  mdc_status s = rfft_launch(op->tw, d.nt, d.nfmax, d.ns, d.nr, d.nr, seg, spec, st);
+  if (s != MDC_OK) return s;
+  return mdc_set_kernel(op, spec, scale * std::sqrt((double)d.nt), col_weight, stream);
+}
+
+mdc_status mch_greens(mdc_op* op, int nv, const float* fminus, const float* fd, const float* fm, float* gminus,
+                      float* gplus_conj, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  return apply_greens(op, nv, fminus, fd, fm, gminus, gplus_conj, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mch_neumann_query(const mdc_op* op, int nv, size_t* work_bytes) {
+  if (!op || !work_bytes) return fail(MDC_EINVAL, "NULL argument");
+  *work_bytes = 2 * align_up((size_t)2 * op->d.nt * op->d.ns * nv * 4, 256);
+  return MDC_OK;
+}
+
+mdc_status mch_neumann(mdc_op* op, const int* onset, int nv, const float* d, float* f, int nterms, void* work,
+                       size_t work_bytes, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if (op->d.ns != op->d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr");
+  if (nv < 1 || 2 * nv > op->d.max_cols) return fail(MDC_EINVAL, "2*nv outside [2, max_cols]");
+  return apply_neumann(op, onset, nv, d, f, nterms, work, work_bytes, static_cast<hipStream_t>(stream));
 }
 
 mdc_status mdc_synth_kernel(mdc_op* op, const mdc_synth_desc* sd, void* stream) {
@@ -653,6 +765,21 @@ mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x,
     return fail(MDC_ENOMEM, "work has %zu bytes, %zu needed", work_bytes, lsqr_work_bytes(op->d, *ld));
   if (hist && !aligned(hist, 8)) return fail(MDC_EINVAL, "hist must be 8-byte aligned");
   return lsqr_run(op, op->d, *ld, b, x, hist, work, static_cast<hipStream_t>(stream));
+}
+
+mdc_status cgls_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist, void* work,
+                      size_t work_bytes, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  mdc_status s = lsqr_check(op, op->d, ld);
+  if (s != MDC_OK) return s;
+  if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if ((s = check_vec(b, "b")) != MDC_OK) return s;
+  if ((s = check_vec(x, "x")) != MDC_OK) return s;
+  if (!work || !aligned(work, 256)) return fail(MDC_EINVAL, "work must be non-NULL and 256-byte aligned");
+  if (work_bytes < lsqr_work_bytes(op->d, *ld))
+    return fail(MDC_ENOMEM, "work has %zu bytes, %zu needed", work_bytes, lsqr_work_bytes(op->d, *ld));
+  if (hist && !aligned(hist, 8)) return fail(MDC_EINVAL, "hist must be 8-byte aligned");
+  return cgls_run(op, op->d, *ld, b, x, hist, work, static_cast<hipStream_t>(stream));
 }
 
 mdc_status mdc_destroy(mdc_op* op) {

@@ -81,11 +81,12 @@ struct FftSeg {
 };
 struct IfftSeg {
   float* out;          // time-domain output [nt][n][nv]
-  const float* ident;  // optional identity term added: out = ident + sign * Theta * y
+  const float* ident;  // optional identity term: out = ident_scale * ident + sign * Theta * y
   const int* onset;    // optional post-window [n][nv], or nullptr
   int conj;            // conjugate the spectrum before the inverse
   int c0;              // first spectral column
   float sign;          // multiplier of the transformed term
+  float ident_scale = 1.0f;
 };
 
 // FFT tables in the resident buffer: tw[k] = exp(-2 pi i k / nt), k < nt.

@@ -247,8 +247,8 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
 template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
     const float2* __restrict__ spec, int ldc, int c0, int conj, const float2* __restrict__ tw, int nfmax,
-    int n, int nv, float scale, float* __restrict__ out, const float* __restrict__ ident,
-    const int* __restrict__ onset, float sign) {
+    int n, int nv, float scale, float* out, const float* ident,
+    const int* __restrict__ onset, float sign, float iscale) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
   float2* lds = sh;
   float2* tws = sh + M * CB;
@@ -331,8 +331,8 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
       if (ident != nullptr) {
         const float4 d0 = *reinterpret_cast<const float4*>(ident + i0);
         const float4 d1 = *reinterpret_cast<const float4*>(ident + i1);
-        o0 = make_float4(o0.x + d0.x, o0.y + d0.y, o0.z + d0.z, o0.w + d0.w);
-        o1 = make_float4(o1.x + d1.x, o1.y + d1.y, o1.z + d1.z, o1.w + d1.w);
+        o0 = make_float4(o0.x + iscale * d0.x, o0.y + iscale * d0.y, o0.z + iscale * d0.z, o0.w + iscale * d0.w);
+        o1 = make_float4(o1.x + iscale * d1.x, o1.y + iscale * d1.y, o1.z + iscale * d1.z, o1.w + iscale * d1.w);
       }
       *reinterpret_cast<float4*>(out + i0) = o0;
       *reinterpret_cast<float4*>(out + i1) = o1;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
         float val = (h == 0 ? z.x : z.y) * scale * sign;
         if (!in_window(t, NT, on)) val = 0.f;
         const size_t idx = (size_t)t * Q + q;
-        if (ident != nullptr) val += ident[idx];
+        if (ident != nullptr) val += iscale * ident[idx];
         out[idx] = val;
       }
     }
@@ -418,7 +418,7 @@ mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const 
     attr = true;
   }
   hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, spec,
-                     ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign);
+                     ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign, s.ident_scale);
   return check_launch("irfft_pad_kernel");
 }
 

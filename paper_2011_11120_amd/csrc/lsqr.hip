@@ -28,6 +28,7 @@ struct Scalars {
   double cx, cw;        // x += cx w ; w = v + cw w
   double inv;           // reciprocal of the last norm (or 1 when it was 0)
   int iter, pad;        // completed iterations (device-side, so every iteration's launches are identical)
+  double gamma, qn, sn, rn;  // CGLS: ||s||^2 of the last step, last norms of q, s, r
   double part[kParts];  // stage-1 partial sums
 };
 
@@ -134,6 +135,41 @@ __global__ __launch_bounds__(kThreads) void update_xw(float* __restrict__ x, flo
   }
 }
 
+// ---------------------------------------------------------------- CGLS ----
+// gamma = ||s||^2 (start), hist[0] = ||r||
+__global__ void cg_init(Scalars* sc, double* hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  sc->gamma = sc->sn * sc->sn;
+  sc->iter = 0;
+  if (hist) hist[0] = sc->rn;
+}
+// alpha = gamma / ||q||^2
+__global__ void cg_alpha(Scalars* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double delta = sc->qn * sc->qn;
+  sc->alpha = delta > 0.0 ? sc->gamma / delta : 0.0;
+}
+// x += alpha p ; r -= alpha q
+__global__ __launch_bounds__(kThreads) void cg_xr(float* __restrict__ x, const float* __restrict__ p,
+                                                  float* __restrict__ r, const float* __restrict__ q, size_t nm,
+                                                  size_t nd, const Scalars* sc) {
+  const float a = (float)sc->alpha;
+  const size_t n = nm > nd ? nm : nd;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
+    if (i < nm) x[i] += a * p[i];
+    if (i < nd) r[i] -= a * q[i];
+  }
+}
+// beta = ||s||^2 / gamma ; gamma = ||s||^2 ; hist[it] = ||r||
+__global__ void cg_beta(Scalars* sc, double* hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double g = sc->sn * sc->sn;
+  sc->beta = sc->gamma > 0.0 ? g / sc->gamma : 0.0;
+  sc->gamma = g;
+  const int it = ++sc->iter;
+  if (hist) hist[it] = sc->rn;
+}
+
 inline int grid_for(size_t n) {
   const size_t b = (n + kThreads - 1) / kThreads;
   return (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
@@ -225,6 +261,10 @@ mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld) 
 
 size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld) { return work_bytes_of(sizes_of(d, ld)); }
 
+__global__ void zero_vec(float* __restrict__ x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] = 0.f;
+}
+
 __global__ void copy_f32(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -302,6 +342,50 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   }
   for (int it = 2; it <= ld.niter; ++it)
     if (hipGraphLaunch(op->lsqr_exec, st) != hipSuccess) return fail(MDC_EDEVICE, "hipGraphLaunch failed");
+  return MDC_OK;
+}
+
+// CGLS (the paper's solver): conjugate gradients on the normal equations, x0 = 0, fixed niter.
+// Vectors FP32 (r, q data-sized; s, p model-sized); gamma, alpha, beta and the norms FP64.
+mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
+                    void* work, hipStream_t st) {
+  const Sizes z = sizes_of(d, ld);
+  char* w = static_cast<char*>(work);
+  Scalars* sc = reinterpret_cast<Scalars*>(w);
+  w += lsqr_scalars_bytes();
+  float* r = reinterpret_cast<float*>(w); w += align_up(z.data * 4, 256);
+  float* q = reinterpret_cast<float*>(w); w += align_up(z.data * 4, 256);
+  float* sv = reinterpret_cast<float*>(w); w += align_up(z.model * 4, 256);
+  float* p = reinterpret_cast<float*>(w);
+  const size_t half = z.model / 2;
+  const int gd = grid_for(z.data), gm = grid_for(z.model), gx = grid_for(z.model > z.data ? z.model : z.data);
+  mdc_status s;
+  // r = b ; s = A^H r ; p = s ; x = 0
+  hipLaunchKernelGGL(copy_f32, dim3(gd), dim3(kThreads), 0, st, r, b, z.data);
+  hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, gd);
+  if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, sv, (const double*)nullptr, 0.0, z.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, gm);
+  hipLaunchKernelGGL(zero_vec, dim3(gm), dim3(kThreads), 0, st, x, z.model);
+  hipLaunchKernelGGL(cg_init, dim3(1), dim3(64), 0, st, sc, hist);
+  for (int it = 1; it <= ld.niter; ++it) {
+    // q = A p ; alpha = gamma / ||q||^2 ; x += alpha p ; r -= alpha q
+    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 0, p, q, half, st)) != MDC_OK) return s;
+    hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, q, z.data, sc);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->qn, gd);
+    hipLaunchKernelGGL(cg_alpha, dim3(1), dim3(64), 0, st, sc);
+    hipLaunchKernelGGL(cg_xr, dim3(gx), dim3(kThreads), 0, st, x, p, r, q, z.model, z.data, sc);
+    hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, gd);
+    // s = A^H r ; beta = ||s||^2 / gamma ; p = s + beta p
+    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
+    hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, sv, z.model, sc);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, gm);
+    hipLaunchKernelGGL(cg_beta, dim3(1), dim3(64), 0, st, sc, hist);
+    hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, p, &sc->beta, 1.0, z.model, sc);
+    if ((s = check_launch("cgls iteration")) != MDC_OK) return s;
+  }
   return MDC_OK;
 }
 

@@ -83,6 +83,11 @@ def _load():
                                 C.POINTER(C.c_int)]),
         "lsqr_query_sizes": (st, [vp, C.POINTER(lsqr_desc), C.POINTER(C.c_size_t)]),
         "lsqr_solve": (st, [vp, C.POINTER(lsqr_desc), vp, vp, vp, vp, C.c_size_t, vp]),
+        "cgls_solve": (st, [vp, C.POINTER(lsqr_desc), vp, vp, vp, vp, C.c_size_t, vp]),
+        "mdc_set_kernel_time": (st, [vp, vp, i, d, vp, vp, C.c_size_t, vp]),
+        "mch_greens": (st, [vp, i, vp, vp, vp, vp, vp, vp]),
+        "mch_neumann_query": (st, [vp, i, C.POINTER(C.c_size_t)]),
+        "mch_neumann": (st, [vp, vp, i, vp, vp, i, vp, C.c_size_t, vp]),
         "serve_request_bytes": (st, [vp, i, C.POINTER(C.c_size_t)]),
         "serve_create": (st, [vp, C.POINTER(serve_geometry), vp, C.c_size_t, C.POINTER(vp)]),
         "serve_submit": (st, [vp, C.POINTER(serve_req), C.POINTER(C.c_uint64)]),
@@ -104,7 +109,8 @@ _lib = _load()
 EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", "mdc_synth_kernel",
            "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mch_forward", "mch_adjoint", "mch_data",
            "mdc_profile", "mdc_profile_read", "mdc_destroy", "mdc_autotune", "mdc_tune_table",
-           "lsqr_query_sizes", "lsqr_solve",
+           "lsqr_query_sizes", "lsqr_solve", "cgls_solve", "mdc_set_kernel_time", "mch_greens",
+           "mch_neumann_query", "mch_neumann",
            "serve_request_bytes", "serve_create", "serve_submit", "serve_poll", "serve_cancel", "serve_drain",
            "serve_stats", "serve_destroy")
 
@@ -223,6 +229,33 @@ def lsqr_query_sizes(h, ld: lsqr_desc) -> int:
 def lsqr_solve(h, ld: lsqr_desc, b, x, hist, work, stream=None):
     _check(_lib.lsqr_solve(h, C.byref(ld), _ptr(b), _ptr(x), _ptr(hist), _ptr(work),
                            C.c_size_t(work.numel() * work.element_size()), _stream(stream)))
+
+
+def cgls_solve(h, ld: lsqr_desc, b, x, hist, work, stream=None):
+    _check(_lib.cgls_solve(h, C.byref(ld), _ptr(b), _ptr(x), _ptr(hist), _ptr(work),
+                           C.c_size_t(work.numel() * work.element_size()), _stream(stream)))
+
+
+def mdc_set_kernel_time(h, g, conj=False, scale=1.0, col_weight=None, temp=None, stream=None):
+    nb = 0 if temp is None else temp.numel() * temp.element_size()
+    _check(_lib.mdc_set_kernel_time(h, _ptr(g), 1 if conj else 0, float(scale), _ptr(col_weight), _ptr(temp),
+                                    C.c_size_t(nb), _stream(stream)))
+
+
+def mch_greens(h, nv, fminus, fd, fm, gminus, gplus_conj, stream=None):
+    _check(_lib.mch_greens(h, int(nv), _ptr(fminus), _ptr(fd), _ptr(fm), _ptr(gminus), _ptr(gplus_conj),
+                           _stream(stream)))
+
+
+def mch_neumann_query(h, nv) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.mch_neumann_query(h, int(nv), C.byref(n)))
+    return n.value
+
+
+def mch_neumann(h, onset, nv, d, f, nterms, work, stream=None):
+    _check(_lib.mch_neumann(h, _ptr(onset), int(nv), _ptr(d), _ptr(f), int(nterms), _ptr(work),
+                            C.c_size_t(work.numel() * work.element_size()), _stream(stream)))
 
 
 def serve_request_bytes(h, nv) -> int:
@@ -399,6 +432,30 @@ class MdcOp:
             h = torch.empty(niter + 1, dtype=torch.float64, device=b.device) if hist else None
         lsqr_solve(self.handle, ld, b, x, h, self._lsqr_work)
         return x, h
+
+    def cgls(self, b, niter, kind=MDC_OP_MDC, nv=1, onset=None):
+        ld = lsqr_desc(kind, nv, niter, None if onset is None else onset.data_ptr())
+        need = lsqr_query_sizes(self.handle, ld)
+        if self._lsqr_work is None or self._lsqr_work.numel() < need:
+            self._lsqr_work = torch.empty(need, dtype=torch.uint8, device=b.device)
+        shape = (2, self.nt, self.nr, nv) if kind == MDC_OP_MARCHENKO else (self.nt, self.nr, nv)
+        x = torch.empty(shape, dtype=torch.float32, device=b.device)
+        h = torch.empty(niter + 1, dtype=torch.float64, device=b.device)
+        cgls_solve(self.handle, ld, b, x, h, self._lsqr_work)
+        return x, h
+
+    def greens(self, fminus, fd, fm):
+        nv = fminus.shape[-1]
+        gm, gp = torch.empty_like(fminus), torch.empty_like(fminus)
+        mch_greens(self.handle, nv, fminus, fd, fm, gm, gp)
+        return gm, gp
+
+    def neumann(self, onset, d, nterms):
+        nv = onset.shape[1]
+        work = torch.empty(mch_neumann_query(self.handle, nv), dtype=torch.uint8, device=d.device)
+        f = torch.empty_like(d)
+        mch_neumann(self.handle, onset, nv, d, f, nterms, work)
+        return f
 
     def close(self):
         if self.handle is not None:
