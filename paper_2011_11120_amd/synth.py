@@ -312,3 +312,10 @@ def random_complex_kernel(nfmax: int, ns: int, nr: int, seed: int = SEED_KERNEL)
     re = gaussian((nfmax, ns, nr), seed, STREAM_KNOISE)
     im = gaussian((nfmax, ns, nr), seed + 1000, STREAM_KNOISE)
     return re + 1j * im
+
+
+def irregular_subset(nx: int, ny: int, fraction: float = 0.5, seed: int = SEED_KERNEL) -> np.ndarray:
+    """Sorted indices of a random `fraction` of an nx-by-ny trace lattice (irregular geometry)."""
+    n = nx * ny
+    keys = rng_uniform(seed, STREAM_SERVE + 1, np.arange(n))
+    return np.sort(np.argsort(keys)[: int(round(fraction * n))])

@@ -160,3 +160,20 @@ def test_marchenko_greens_mdd_chain_matches_oracle(mdcmod):
     # adjoint-only imaging (correlation, the MDD section's adjoint) equals the oracle's
     img = mdd.adjoint(gm)
     assert relmax(host(img), om.mdc_adjoint(Kmdd, gmo)) < 1e-4
+
+
+def test_irregular_geometry_voronoi_weights(mdcmod):
+    """Irregular receivers (a random half of the lattice) with Voronoi areal weights per column."""
+    from paper_2011_11120_amd import geometry
+    spec = synth.KernelSpec(nt=128, nfmax=40, nx=8, dx=15.0, nev=6, kappa=1.0)
+    idx = synth.irregular_subset(spec.nx, spec.nx, 0.5)
+    gx, gy = synth.grid_xy(spec.nx, spec.nx, spec.dx)
+    w = geometry.voronoi_areas(gx[idx], gy[idx], bounds=(-7.5, 112.5, -7.5, 112.5), pixel=0.5)
+    K = synth.kernel_block(spec, np.arange(spec.nfmax), np.arange(spec.n), idx)
+    op = mdcmod.MdcOp(spec.nt, spec.nfmax, spec.n, idx.size, max_cols=3)
+    op.set_kernel(dev(K, torch.complex64), col_weight=dev(w))
+    Kw = K * w[None, None, :]
+    x = synth.gaussian((spec.nt, idx.size, 3), seed=21)
+    y = synth.gaussian((spec.nt, spec.n, 3), seed=22)
+    assert relmax(host(op.forward(dev(x))), om.mdc_forward(Kw, x)) < TOL
+    assert relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(Kw, y)) < TOL
