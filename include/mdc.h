@@ -36,6 +36,10 @@
  *   time vectors   float   [nt][n][nv]
  *   kernel input   float2  [nfmax][ns][nr]   (complex64: re, im)
  *   onsets         int32   [n][nv]           (window half-width in samples)
+ *
+ * Windows: an onset o >= 0 keeps the samples with |lag(t)| < o (two-sided); an
+ * onset o < 0 keeps 0 <= lag(t) < -o (one-sided, causal), with lag(t) = t for
+ * t < nt/2 and t - nt otherwise.
  */
 #ifndef MDC_H
 #define MDC_H
@@ -151,7 +155,7 @@ mdc_status mdc_adjoint(mdc_op* op, const float* y, float* x, int nv, void* strea
  *   forward  (o0, o1) = (in0 - Theta R in1,  in1 - Theta R* in0)
  *   adjoint  (o0, o1) = (in0 - R*^H Theta in1,  in1 - R^H Theta in0)
  * R uses the kernel, R* its complex conjugate (no transpose).  Theta[t][s][v] = 1
- * when |lag(t)| < onset[s][v], lag(t) = t for t < nt/2 and t - nt otherwise.
+ * when |lag(t)| < onset[s][v] (onset >= 0; the window encoding above).
  * One pass over the kernel serves both blocks (columns [R-input | conj R*-input]).
  * All arrays are device arrays [nt][n][nv]; outputs must not alias inputs. */
 mdc_status mch_forward(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1,
@@ -216,7 +220,10 @@ typedef struct {
   mdc_opkind kind;
   int nv;             /* virtual points */
   int niter;          /* iterations (>= 0) */
-  const int* onset;   /* Marchenko window onsets [n][nv] (device), else NULL */
+  const int* onset;   /* MDC_OP_MARCHENKO: window onsets [n][nv] (device), required.
+                         MDC_OP_MDC: optional model preconditioner P [nr][nv] (device) in the
+                         same encoding, so the solve is min ||b - C P z||, x = P z (Discussion
+                         section: causal time windowing of the MDD unknown); NULL = none */
 } lsqr_desc;
 
 /* Bytes of the workspace lsqr_solve needs for this descriptor. */

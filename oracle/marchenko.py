@@ -30,9 +30,17 @@ def lag_index(nt: int) -> np.ndarray:
 
 
 def theta(nt: int, onset: np.ndarray) -> np.ndarray:
-    """Theta[t, s, v] in {0, 1} from integer onsets [n, nv]."""
-    lag = np.abs(lag_index(nt))
-    return (lag[:, None, None] < onset[None, :, :]).astype(np.float64)
+    """Theta[t, s, v] in {0, 1} from integer onsets [n, nv].
+
+    onset >= 0: the two-sided Marchenko window |lag| < onset (Eq.5).  onset < 0: the
+    one-sided window 0 <= lag < -onset, a causal time-domain preconditioner for the
+    MDD unknown (Discussion section).
+    """
+    lag = lag_index(nt)[:, None, None]
+    on = np.asarray(onset)[None, :, :]
+    two = np.abs(lag) < on
+    one = (lag >= 0) & (lag < -on)
+    return np.where(on >= 0, two, one).astype(np.float64)
 
 
 def forward(K: np.ndarray, onset: np.ndarray, fm: np.ndarray, fp: np.ndarray):

@@ -188,7 +188,10 @@ mdc_status check_vec(const void* p, const char* name) {
   return MDC_OK;
 }
 
-mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st) {
+// pre: optional window [nr][nv] on the model side (a time-domain preconditioner P, so the
+// operator is C P, adjoint P C^H), or nullptr.
+mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st,
+                       const int* pre = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
   if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
@@ -201,7 +204,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   float2* spec_out = adjoint ? op->specR : op->specS;
   {
     Stage t(op, 0, st);
-    FftSeg seg{in, nullptr, 0, 0};
+    FftSeg seg{in, adjoint ? nullptr : pre, 0, 0};
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, nin, nv, nv, seg, spec_in, st)) != MDC_OK) return s;
   }
   {
@@ -210,7 +213,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   }
   {
     Stage t(op, 3, st);
-    IfftSeg seg{out, nullptr, nullptr, 0, 0, 1.0f};
+    IfftSeg seg{out, nullptr, adjoint ? pre : nullptr, 0, 0, 1.0f};
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, nout, nv, nv, seg, spec_out, st)) != MDC_OK) return s;
   }
   return MDC_OK;
@@ -409,7 +412,7 @@ mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint,
                     size_t half, hipStream_t st) {
   if (kind == MDC_OP_MARCHENKO)
     return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st);
-  return apply_plain(op, in, out, nv, adjoint, st);
+  return apply_plain(op, in, out, nv, adjoint, st, onset);
 }
 }  // namespace mdc
 

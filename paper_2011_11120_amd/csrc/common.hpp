@@ -65,9 +65,12 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 
 // ---------------------------------------------------- window (Theta) -------
 // Theta[t][s][v] = 1 when |lag(t)| < onset, lag(t) = t (t < nt/2) else t - nt.
+// A negative onset -h selects the one-sided (causal) window 0 <= lag(t) < h, the
+// time-domain preconditioner that confines a solution to non-negative times.
 __device__ __forceinline__ bool in_window(int t, int nt, int onset) {
-  int lag = (2 * t < nt) ? t : nt - t;
-  return lag < onset;
+  const bool causal = 2 * t < nt;
+  if (onset < 0) return causal && t < -onset;
+  return (causal ? t : nt - t) < onset;
 }
 
 // --------------------------------------------------------- launchers -------

@@ -160,6 +160,39 @@ def test_marchenko_greens_mdd_chain_matches_oracle(mdcmod):
     # adjoint-only imaging (correlation, the MDD section's adjoint) equals the oracle's
     img = mdd.adjoint(gm)
     assert relmax(host(img), om.mdc_adjoint(Kmdd, gmo)) < 1e-4
+    # MDD with the causal time preconditioner (the reflectivity lives at non-negative times)
+    causal = np.full((nF, nF), -nt, dtype=np.int32)
+    rc, _ = mdd.lsqr(gm, 15, nv=nF, onset=dev(causal, torch.int32))
+    P = omc.theta(nt, causal)
+    rco, _ = ol.lsqr(lambda v: [om.mdc_forward(Kmdd, P * v[0])], lambda u: [P * om.mdc_adjoint(Kmdd, u[0])],
+                     [gmo], 15)
+    rcg = host(rc)
+    assert np.all(rcg[nt // 2:] == 0)
+    err = rel2(rcg, rco[0])
+    print(f"causal MDD chain: relative error {err:.2e}", flush=True)
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("solver", ["lsqr", "cgls"])
+def test_preconditioned_mdc_solvers_match_oracle(mdcmod, solver):
+    """Plain-MDC solves with a model window P (one-sided and two-sided onsets mixed)."""
+    nt, nfmax, ns, nr, nv, niter = 64, 25, 20, 12, 3, 10
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=41)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv)
+    op.set_kernel(dev(K, torch.complex64))
+    pre = (np.arange(nr * nv).reshape(nr, nv) % 7 - 3) * 5
+    pre[0, 0] = -nt
+    pre = pre.astype(np.int32)
+    b = synth.gaussian((nt, ns, nv), seed=42)
+    run = op.lsqr if solver == "lsqr" else op.cgls
+    x, hist = run(dev(b), niter, nv=nv, onset=dev(pre, torch.int32))
+    P = omc.theta(nt, pre)
+    ref = ol.lsqr if solver == "lsqr" else ol.cgls
+    xr, hr = ref(lambda v: [om.mdc_forward(K, P * v[0])], lambda u: [P * om.mdc_adjoint(K, u[0])], [b], niter)
+    xg = host(x)
+    assert np.all(xg[P == 0] == 0)
+    assert rel2(xg, xr[0]) < TOL
+    assert np.max(np.abs(host(hist) - hr) / hr[0]) < TOL
 
 
 def test_irregular_geometry_voronoi_weights(mdcmod):

@@ -140,3 +140,36 @@ def test_greens_single_scattering():
     gm, gpc = om.greens(K, np.zeros_like(fd), fd)
     assert rel(gm, omdc.conv_time(k, fd)) < 1e-12
     assert rel(gpc, fd) < 1e-14
+
+
+def test_window_encoding_by_enumeration():
+    """Two-sided (onset >= 0) and one-sided causal (onset < 0) windows, sample by sample."""
+    nt = 12
+    onset = np.array([[0, 3], [-1, -4], [-12, 7]], dtype=np.int32)
+    th = om.theta(nt, onset)
+    for s in range(3):
+        for v in range(2):
+            o = onset[s, v]
+            for t in range(nt):
+                lag = t if t < nt // 2 else t - nt
+                keep = abs(lag) < o if o >= 0 else 0 <= lag < -o
+                assert th[t, s, v] == (1.0 if keep else 0.0)
+    assert np.array_equal(th[:, 2, 0], (np.arange(nt) < nt // 2).astype(float))
+
+
+def test_causal_preconditioned_lsqr_is_restricted_lstsq():
+    """LSQR on C P (P the causal window) converges to least squares over the causal samples only."""
+    nt, nx = 16, 2
+    k, K, _ = _marchenko_case(nt=nt, nx=nx, scale=3.0)
+    n = nx * nx
+    pre = np.full((n, 1), -nt, dtype=np.int32)
+    P = om.theta(nt, pre)
+    b = synth.gaussian((nt, n, 1), seed=31)
+    A = lambda v: [omdc.mdc_forward(K, P * v[0])]
+    AH = lambda u: [P * omdc.mdc_adjoint(K, u[0])]
+    x, _ = ol.lsqr(A, AH, [b], 80)
+    assert np.all(x[0][nt // 2:] == 0)
+    C = _conv_matrix(k)
+    cols = np.concatenate([np.arange(t * n, (t + 1) * n) for t in range(nt // 2)])
+    z = np.linalg.lstsq(C[:, cols], b[:, :, 0].ravel(), rcond=None)[0]
+    assert rel(x[0][: nt // 2, :, 0].ravel(), z) < 1e-8
