@@ -84,7 +84,9 @@ typedef struct {
 const char* mdc_last_error(void);
 
 /* Bytes of the resident buffer (kernel + tables, 256-byte aligned pieces) and
- * of the per-apply workspace (spectra of max_cols columns). */
+ * of the per-apply workspace (spectra of max_cols columns; for the 16-bit
+ * formats also one spectrum split into bf16 hi and lo parts, padded to
+ * multiples of 64 columns and 32 traces, for the matrix-core product). */
 mdc_status mdc_query_sizes(const mdc_desc* desc, size_t* resident_bytes, size_t* workspace_bytes);
 
 /* Create an operator over caller-owned device buffers `resident` and `workspace`

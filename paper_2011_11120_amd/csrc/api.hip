@@ -64,7 +64,7 @@ static mdc_status run_family(const mdc_op* op, int fam, int adjoint, const float
   if (d.prec == MDC_FP32)
     return gemm_launch(d, static_cast<const float2*>(op->kstore), ldk, adjoint, in, out, ncols, st,
                        fam == kFamGemm32 ? 32 : 64);
-  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, st);
+  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, op->bsplit, st);
 }
 
 int choose_family(const mdc_op* op, int adjoint, int ncols) {
@@ -131,7 +131,7 @@ mdc_status check_desc(const mdc_desc* d) {
 
 struct Layout {
   size_t tw, fscale, kstore, resident;
-  size_t specR, specS, work;
+  size_t specR, specS, bsplit, work;
 };
 
 Layout layout_of(const mdc_desc& d) {
@@ -144,6 +144,8 @@ Layout layout_of(const mdc_desc& d) {
   off = 0;
   L.specR = off; off = align_up(off + (size_t)d.nfmax * d.nr * d.max_cols * 8, kAlign);
   L.specS = off; off = align_up(off + (size_t)d.nfmax * d.ns * d.max_cols * 8, kAlign);
+  L.bsplit = off;
+  if (d.prec != MDC_FP32) off = align_up(off + gemm16_split_bytes(d), kAlign);
   L.work = off;
   return L;
 }
@@ -446,6 +448,7 @@ mdc_status mdc_create(const mdc_desc* desc, void* resident, void* workspace, voi
   op->kstore = op->resident + L.kstore;
   op->specR = reinterpret_cast<float2*>(op->work + L.specR);
   op->specS = reinterpret_cast<float2*>(op->work + L.specS);
+  op->bsplit = desc->prec != MDC_FP32 ? reinterpret_cast<unsigned int*>(op->work + L.bsplit) : nullptr;
   op->kernel_ready = false;
   op->prof = false;
   // FFT table in FP64, rounded once: tw[k] = exp(-2 pi i k / nt)

@@ -28,6 +28,7 @@ struct mdc_op {
   void* kstore;      // stored kernel
   float2* specR;     // [nfmax][nr][max_cols]
   float2* specS;     // [nfmax][ns][max_cols]
+  unsigned int* bsplit;  // split spectra of the 16-bit matrix-core product (16-bit formats), else nullptr
   bool kernel_ready;
   std::vector<float2> tw_host;
   // profiling

@@ -1,41 +1,75 @@
-// Per-frequency complex kernel product on the bf16 matrix cores
-// (v_mfma_f32_16x16x32_bf16, FP32 accumulate) for the 16-bit storage formats:
-// the reduced-precision variants of the many-point product (Eq.4 slices).
+// Per-frequency complex kernel product on the 16-bit matrix cores for the
+// reduced-precision storage formats: the many-point product (Eq.4 slices)
+// with a kernel of 4 or 8 bytes per complex value.
 //
-// Operands are split into bf16 hi + lo parts so the product keeps close to
-// FP32 accuracy (the split-operand scheme of Henry, Tang & Heinecke,
-// ARITH 2019):  K X ~ Khi Xhi + Khi Xlo + Klo Xhi.
-//   BF16X2: K stored as hi + lo (8 bytes per complex), three products.
-//   FP16S:  K stored as FP16 scaled by a power of two per frequency (4 bytes);
-//           every FP16 value splits exactly into bf16 hi + lo in registers,
-//           three products, the scale divided out of the result.
-//   BF16:   K stored as bf16 (4 bytes), two products (Khi Xhi + Khi Xlo).
-// The spectra X (or Y) arrive in FP32 and are split when staged into LDS.
+// Operands are split into hi + lo parts so the product keeps close to FP32
+// accuracy (the split-operand scheme of Henry, Tang & Heinecke, ARITH 2019),
+// FP32 accumulation throughout:
+//   BF16X2: K stored as bf16 hi + lo (8 bytes per complex); spectra split into
+//           bf16 hi + lo; three products Khi Xhi + Khi Xlo + Klo Xhi
+//           (v_mfma_f32_32x32x16_bf16).
+//   BF16:   K stored as bf16 (4 bytes); two products Khi Xhi + Khi Xlo.
+//   FP16S:  K stored as FP16 of K * 2^e_f (4 bytes, power-of-two scale per
+//           frequency); spectra split into FP16 hi + lo of X * 2^s_f, s_f from a
+//           per-frequency maximum; two products on v_mfma_f32_32x32x16_f16; both
+//           scales divided out of the result (exact, powers of two).
 //
-// The complex product is the same real embedding as the FP32 kernel: the
-// interleaved kernel is a real ns x 2nr matrix, and the B operand is built
-// from complex values at fragment-read time (forward: (c, -d) / (d, c) pairs;
-// adjoint: (e, f) / (f, -e) pairs), here by flipping and swapping the halves of
-// 32-bit bf16 pairs.  One MFMA k-step consumes 16 complex kernel columns.
-// Tiles: 128 output rows x 64 complex columns per 256-thread workgroup (four
-// waves of 64 x 64 real outputs), 32-column slabs staged through LDS (the
-// adjoint stages the kernel transposed so fragments stay contiguous), register
-// prefetch of the next slab, XCD-aware workgroup numbering.
+// The complex product is the real embedding used by the FP32 kernel: the
+// interleaved kernel is a real ns x 2nr matrix (forward) or its transpose
+// (adjoint), and the spectra enter as 2x2 real blocks, forward (c, -d | d, c),
+// adjoint (e, f | f, -e).
+//
+// Data flow per apply:
+//  1. bsplit_kernel transposes the FP32 spectra [f][k][v] into split pair words
+//     [f][v][k/4][hi 4 words | lo 4 words], zero-padded to whole tiles, so every
+//     row tile stages them with plain 16-byte copies (FP16S first takes the
+//     per-frequency maximum, spec_max_kernel).
+//  2. gemm16_kernel: a 256-thread workgroup computes 256 output rows x 64 complex
+//     columns of one frequency.  Wave w owns rows 64w .. 64w + 63 (two blocks of
+//     32 rows) for all 64 complex columns, as eight 32x32 MFMA blocks: block ni
+//     holds the real part (ni even) or imaginary part (ni odd) of complex columns
+//     32 (ni / 2) .. 32 (ni / 2) + 31.
+//     * The kernel is never shared between waves, so it bypasses LDS: each lane
+//       loads its own fragment registers five 16-column k-steps ahead of use
+//       (ring of six register sets).  Forward: four consecutive complex values
+//       of one kernel row; adjoint: one kernel column at four consecutive rows.
+//     * The split spectra go through LDS, triple-buffered per 32-column slab,
+//       both embedded variants stored side by side (the sign/swap is applied
+//       once per slab at the store, not per fragment).  Spectra fragments are
+//       read one half-step (8 complex columns) ahead of their MFMAs.
+//     * The 32x32 MFMA shape issues back to back from one wave per SIMD, so the
+//       inner loop holds only fragment loads and MFMAs; one workgroup per CU
+//       leaves each wave the register file for the deep ring and accumulators.
+//     * Loads are never predicated (a predicated load makes the compiler wait
+//       for every outstanding load at the merge, draining the ring): indices
+//       past the end are clamped onto valid kernel data, which meets zero
+//       spectra or feeds outputs that are not stored.
+//     * Workgroups are numbered so that the row tiles of one frequency run on
+//       one XCD (hardware deals workgroups round-robin over the 8 XCDs), which
+//       keeps that frequency's spectra in one L2.
+#include <algorithm>
+#include <cstdlib>
+#include <type_traits>
+
 #include "common.hpp"
 #include "store.hpp"
 
 namespace mdc {
 namespace {
 
-typedef float f4v __attribute__((ext_vector_type(4)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;
-constexpr int BM = 128;  // output rows per workgroup
-constexpr int BN = 64;   // complex output columns per workgroup
-constexpr int BK = 32;   // complex reduction columns per slab
-constexpr int LDW = 36;  // 32-bit words per LDS row: 32 complex + 4 pad
+constexpr int BM = 256;                 // output rows per workgroup (4 waves x 64)
+constexpr int BN = 64;                  // complex output columns per workgroup
+constexpr int BK = 32;                  // complex reduction columns per LDS slab
+constexpr int KSTEP_PAD = 96;           // reduction length padded to six 16-column k-steps
+constexpr int LDB = 36;                 // words per LDS row: 32 reduction indices + 4 pad
+constexpr int HALF = 2 * BN * LDB;      // one (hi or lo) slab: 128 real columns
+constexpr int BUF = 2 * HALF + 64;      // hi | lo, lo shifted by 32 banks (conflict-free stores)
 
 __device__ __forceinline__ unsigned int split_lo(float x, unsigned int hb) {
   return bf16_rne_bits(x - bf16_bits_to_f(hb));
@@ -48,19 +82,26 @@ __device__ __forceinline__ void split_pair(float re, float im, unsigned int& hi,
 }
 __device__ __forceinline__ unsigned int swap16(unsigned int w) { return (w >> 16) | (w << 16); }
 
-template <int FMT>
-constexpr int a_loads() { return FMT == MDC_BF16X2 ? 8 : 4; }
+// Power-of-two scale of the FP16 spectra split: largest s = 2^e with max * s <= 2^14.
+__device__ __forceinline__ float spec_scale(float mx) {
+  if (!(mx > 0.f)) return 1.0f;
+  int e;
+  frexpf(mx, &e);  // mx in [2^(e-1), 2^e)
+  return ldexpf(1.0f, 14 - e);
+}
 
 template <int FMT, bool ADJ>
-__global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restrict__ K, const float* __restrict__ fscale,
-                                                             int ns, int nr, int ldk, const float2* __restrict__ Bsrc,
+__global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restrict__ K,
+                                                             const float* __restrict__ fscale,
+                                                             const float* __restrict__ bmax, int ns, int nr, int ldk,
+                                                             const unsigned int* __restrict__ Bp, int KG, int NCP,
                                                              float2* __restrict__ Cdst, int ncols, int tiles_m,
                                                              int tiles_n, int nblocks) {
-  __shared__ __attribute__((aligned(16))) unsigned int Ah[BM * LDW];
-  __shared__ __attribute__((aligned(16))) unsigned int Al[BM * LDW];
-  __shared__ __attribute__((aligned(16))) unsigned int Bh[BN * LDW];
-  __shared__ __attribute__((aligned(16))) unsigned int Bl[BN * LDW];
-  constexpr bool HAS_LO = FMT != MDC_BF16;
+  __shared__ __attribute__((aligned(16))) unsigned int Bs[3 * BUF];
+  constexpr bool X2 = FMT == MDC_BF16X2;
+  constexpr bool F16 = FMT == MDC_FP16S;
+  using frag = typename std::conditional<F16, h8v, bf8v>::type;
+  constexpr int NA = X2 ? 8 : 4;  // u4v per lane per k-step: 2 row blocks x 2 k-halves x (hi, lo | one)
 
   const int b = blockIdx.x;
   const int q8 = nblocks >> 3, rem = nblocks & 7, xcd = b & 7;
@@ -69,208 +110,283 @@ __global__ __launch_bounds__(kThreads, 2) void gemm16_kernel(const char* __restr
   const int f = L / tiles_per_f;
   const int t = L - f * tiles_per_f;
   const int mt = t % tiles_m, nt = t / tiles_m;
-  const int M = ADJ ? nr : ns;
-  const int KD = ADJ ? ns : nr;
   const int m0 = mt * BM, n0 = nt * BN;
-  const size_t rowb = (FMT == MDC_BF16X2) ? (size_t)ldk * 8 : (size_t)ldk * 4;
-  const char* Kf = K + (size_t)f * ns * rowb;
-  const float2* Bf = Bsrc + (size_t)f * KD * ncols;
+  const int M = ADJ ? nr : ns;
+  const size_t rowb = X2 ? (size_t)ldk * 8 : (size_t)ldk * 4;
+  const unsigned int* Bf = Bp + ((size_t)f * NCP + n0) * KG * 8;
   float* Cf = reinterpret_cast<float*>(Cdst + (size_t)f * M * ncols);
+  const char* Kf = K + (size_t)f * ns * rowb;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int li = lane & 15, kb = lane >> 4;
+  const int l32 = lane & 31, kh = lane >> 5;
+  const int nsteps = KG >> 2;  // 16-column k-steps, a multiple of 6
+  const int nslabs = nsteps >> 1;
 
-  u4v pa[a_loads<FMT>()];
-  float2 pb[8];
-
-  auto load_slab = [&](int k0) {
+  // this lane's two output rows (kernel rows forward, kernel columns adjoint), clamped
+  size_t aoff[2];
 #pragma unroll
-    for (int q = 0; q < a_loads<FMT>(); ++q) {
-      const int idx = tid + kThreads * q;
-      u4v v = u4v{0u, 0u, 0u, 0u};
-      if constexpr (FMT == MDC_BF16X2) {
-        if (!ADJ) {
-          const int row = idx >> 4, c = idx & 15, gi = c >> 1, half = c & 1;
-          const int m = m0 + row, col = k0 + 4 * gi;
-          if (m < ns && col < ldk)
-            v = *reinterpret_cast<const u4v*>(Kf + (size_t)m * rowb + (size_t)(col >> 2) * 32 + half * 16);
-        } else {  // consecutive lanes take consecutive kernel rows (conflict-free transposed LDS stores)
-          const int srow = idx & 31, c = idx >> 5, gi = c >> 1, half = c & 1;
-          const int s = k0 + srow, col = m0 + 4 * gi;
-          if (s < ns && col < ldk)
-            v = *reinterpret_cast<const u4v*>(Kf + (size_t)s * rowb + (size_t)(col >> 2) * 32 + half * 16);
-        }
-      } else {
-        if (!ADJ) {
-          const int row = idx >> 3, c4 = idx & 7;
-          const int m = m0 + row, col = k0 + 4 * c4;
-          if (m < ns && col < ldk) v = *reinterpret_cast<const u4v*>(Kf + (size_t)m * rowb + (size_t)col * 4);
-        } else {
-          const int srow = idx & 31, c4 = idx >> 5;
-          const int s = k0 + srow, col = m0 + 4 * c4;
-          if (s < ns && col < ldk) v = *reinterpret_cast<const u4v*>(Kf + (size_t)s * rowb + (size_t)col * 4);
-        }
-      }
-      pa[q] = v;
-    }
+  for (int rb = 0; rb < 2; ++rb) {
+    const int rr = min(m0 + wave * 64 + rb * 32 + l32, M - 1);
+    aoff[rb] = !ADJ ? (size_t)rr * rowb : (X2 ? (size_t)(rr >> 2) * 32 + (rr & 3) * 4 : (size_t)rr * 4);
+  }
+  // kernel fragments of k-step j: r[q] (q = 2 rb + h) holds the lane's four reduction
+  // indices 16 j + 8 h + 4 kh .. + 3 of row block rb (X2: r[2q] hi, r[2q + 1] lo)
+  auto load_a = [&](int j, u4v (&r)[NA]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = tid + kThreads * q;
-      const int krow = idx & 31, c2 = idx >> 5;  // consecutive lanes: consecutive LDS words
-      const int kk = k0 + krow, v = n0 + 2 * c2;
-      const float2* src = Bf + (size_t)kk * ncols;
-      pb[2 * q] = (kk < KD && v < ncols) ? src[v] : make_float2(0.f, 0.f);
-      pb[2 * q + 1] = (kk < KD && v + 1 < ncols) ? src[v + 1] : make_float2(0.f, 0.f);
-    }
-  };
-
-  auto store_slab = [&]() {
-#pragma unroll
-    for (int q = 0; q < a_loads<FMT>(); ++q) {
-      const int idx = tid + kThreads * q;
-      const u4v v = pa[q];
-      const unsigned int w[4] = {v.x, v.y, v.z, v.w};
-      unsigned int hi[4], lo[4];
-      unsigned int* dst_h;
-      unsigned int* dst_l;
-      int rowl, coll;  // forward: (row, first column) ; adjoint: (first r, s)
-      if constexpr (FMT == MDC_BF16X2) {
-        const int half = ADJ ? ((idx >> 5) & 1) : (idx & 1);
-        if (!ADJ) { rowl = idx >> 4; coll = 4 * ((idx & 15) >> 1); }
-        else { coll = idx & 31; rowl = 4 * ((idx >> 5) >> 1); }
-#pragma unroll
-        for (int h = 0; h < 4; ++h) hi[h] = w[h];
-        dst_h = half ? Al : Ah;
-        dst_l = nullptr;
+      const int h = q & 1, rb = q >> 1;
+      const int g = 4 * min(j, nsteps - 1) + 2 * h + kh;  // group of four reduction indices
+      if constexpr (!ADJ) {
+        const char* p = Kf + aoff[rb] + (size_t)min(g, (ldk >> 2) - 1) * (X2 ? 32 : 16);
+        r[X2 ? 2 * q : q] = *reinterpret_cast<const u4v*>(p);
+        if constexpr (X2) r[2 * q + 1] = *reinterpret_cast<const u4v*>(p + 16);
       } else {
-        if (!ADJ) { rowl = idx >> 3; coll = 4 * (idx & 7); }
-        else { coll = idx & 31; rowl = 4 * (idx >> 5); }
+        unsigned int wh[4], wl[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          if constexpr (FMT == MDC_FP16S) {
-            const float re = f16_bits_to_f(w[h] & 0xFFFFu), im = f16_bits_to_f(w[h] >> 16);
-            split_pair(re, im, hi[h], lo[h]);  // exact: an FP16 value is bf16 hi + lo
-          } else {
-            hi[h] = w[h];
-            lo[h] = 0u;
-          }
+        for (int i = 0; i < 4; ++i) {
+          const char* p = Kf + (size_t)min(4 * g + i, ns - 1) * rowb + aoff[rb];
+          wh[i] = *reinterpret_cast<const unsigned int*>(p);
+          if constexpr (X2) wl[i] = *reinterpret_cast<const unsigned int*>(p + 16);
         }
-        dst_h = Ah;
-        dst_l = HAS_LO ? Al : nullptr;
-      }
-      if (!ADJ) {
-        *reinterpret_cast<u4v*>(&dst_h[rowl * LDW + coll]) = u4v{hi[0], hi[1], hi[2], hi[3]};
-        if (dst_l) *reinterpret_cast<u4v*>(&dst_l[rowl * LDW + coll]) = u4v{lo[0], lo[1], lo[2], lo[3]};
-      } else {  // transposed: A[r][s]
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          dst_h[(rowl + h) * LDW + coll] = hi[h];
-          if (dst_l) dst_l[(rowl + h) * LDW + coll] = lo[h];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + kThreads * q;
-      const int krow = idx & 31, c2 = idx >> 5;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        unsigned int hi, lo;
-        split_pair(pb[2 * q + h].x, pb[2 * q + h].y, hi, lo);
-        Bh[(2 * c2 + h) * LDW + krow] = hi;
-        Bl[(2 * c2 + h) * LDW + krow] = lo;
+        r[X2 ? 2 * q : q] = u4v{wh[0], wh[1], wh[2], wh[3]};
+        if constexpr (X2) r[2 * q + 1] = u4v{wl[0], wl[1], wl[2], wl[3]};
       }
     }
   };
+  // split spectra of one slab: 64 columns x 8 groups x (hi, lo), four 16-byte pieces per thread
+  u4v pb[4];
+  auto load_b = [&](int sl) {
+    const int g0 = min(sl, nslabs - 1) * (BK / 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + kThreads * q;
+      const int v = idx >> 4, gi = (idx & 15) >> 1, half = idx & 1;
+      pb[q] = *reinterpret_cast<const u4v*>(Bf + ((size_t)v * KG + g0 + gi) * 8 + half * 4);
+    }
+  };
+  // both embedded variants: forward (c, -d) | (d, c), adjoint (e, f) | (f, -e)
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + kThreads * q;
+      const int v = idx >> 4, gi = (idx & 15) >> 1, half = idx & 1;
+      const u4v w = pb[q];
+      const u4v sw = u4v{swap16(w.x), swap16(w.y), swap16(w.z), swap16(w.w)};
+      const int row0 = (v >> 5) * 64 + (v & 31);
+      unsigned int* base = Bs + buf * BUF + half * (HALF + 32) + 4 * gi;
+      *reinterpret_cast<u4v*>(base + row0 * LDB) = ADJ ? w : w ^ 0x80000000u;
+      *reinterpret_cast<u4v*>(base + (row0 + 32) * LDB) = ADJ ? sw ^ 0x80000000u : sw;
+    }
+  };
+  // spectra fragments of one half-step (k-step ks of a slab, half h) from LDS buffer buf
+  struct Frags {
+    frag hi[4], lo[4];
+  };
+  auto read_b = [&](Frags& F, int buf, int ks, int h) {
+    const unsigned int* Bh = Bs + buf * BUF;
+    const unsigned int* Bl = Bh + HALF + 32;
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const int off = (ni * 32 + l32) * LDB + ks * 16 + 8 * h + 4 * kh;
+      F.hi[ni] = __builtin_bit_cast(frag, *reinterpret_cast<const u4v*>(Bh + off));
+      F.lo[ni] = __builtin_bit_cast(frag, *reinterpret_cast<const u4v*>(Bl + off));
+    }
+  };
 
-  f4v acc[4][4];
+  f16v acc[2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[rb][i][e] = 0.f;
 
-  const int nslabs = (KD + BK - 1) / BK;
-  load_slab(0);
-  for (int sl = 0; sl < nslabs; ++sl) {
-    __syncthreads();  // previous slab fully consumed
-    store_slab();
-    __syncthreads();
-    if (sl + 1 < nslabs) load_slab((sl + 1) * BK);
+  auto mma = [](frag a, frag bb, f16v c) {
+    if constexpr (F16) return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bb, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, c, 0, 0, 0);
+  };
+  auto compute = [&](const u4v (&r)[NA], const Frags& F, int h) {
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const int wo = ks * 16 + 4 * kb;  // word offset of this lane's 4 complex values
-      bf8v ah[4], al[4], bh[4], bl[4];
+    for (int rb = 0; rb < 2; ++rb) {
+      const int q = 2 * rb + h;
+      const frag ah = __builtin_bit_cast(frag, r[X2 ? 2 * q : q]);
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        const int row = wm * 64 + mi * 16 + li;
-        ah[mi] = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4v*>(&Ah[row * LDW + wo]));
-        if constexpr (HAS_LO) al[mi] = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4v*>(&Al[row * LDW + wo]));
+      for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(ah, F.hi[ni], acc[rb][ni]);
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(ah, F.lo[ni], acc[rb][ni]);
+      if constexpr (X2) {
+        const frag al = __builtin_bit_cast(frag, r[2 * q + 1]);
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(al, F.hi[ni], acc[rb][ni]);
       }
+    }
+  };
+
+  // Pipeline: kernel fragments five k-steps ahead in a ring of six register sets;
+  // spectra staged from memory at the start of slab sl, stored to LDS buffer
+  // (sl + 2) % 3 at its end; spectra fragments read one half-step ahead.  An
+  // iteration covers six k-steps = three slabs = one turn of both rings, so every
+  // ring and buffer index below is a compile-time constant.
+  u4v ring[6][NA];
+  Frags F[2];
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        const int n = wn * 64 + ni * 16 + li;  // real column within the tile
-        const int v = n >> 1, jj = n & 1;
-        u4v wh = *reinterpret_cast<const u4v*>(&Bh[v * LDW + wo]);
-        u4v wl = *reinterpret_cast<const u4v*>(&Bl[v * LDW + wo]);
-        if (!ADJ) {
-          if (jj == 0) { wh ^= 0x80000000u; wl ^= 0x80000000u; }   // (c, -d)
-          else {                                                     // (d, c)
-            wh = u4v{swap16(wh.x), swap16(wh.y), swap16(wh.z), swap16(wh.w)};
-            wl = u4v{swap16(wl.x), swap16(wl.y), swap16(wl.z), swap16(wl.w)};
-          }
-        } else if (jj == 1) {                                        // (f, -e)
-          wh = u4v{swap16(wh.x), swap16(wh.y), swap16(wh.z), swap16(wh.w)} ^ 0x80000000u;
-          wl = u4v{swap16(wl.x), swap16(wl.y), swap16(wl.z), swap16(wl.w)} ^ 0x80000000u;
-        }
-        bh[ni] = __builtin_bit_cast(bf8v, wh);
-        bl[ni] = __builtin_bit_cast(bf8v, wl);
+  for (int i = 0; i < 5; ++i) load_a(i, ring[i]);
+  load_b(0);
+  store_b(0);
+  load_b(1);
+  store_b(1);
+  __syncthreads();
+  read_b(F[0], 0, 0, 0);
+  for (int j = 0; j < nsteps; j += 6) {
+#pragma unroll
+    for (int p = 0; p < 12; ++p) {  // half-step p: k-step i = p / 2 of the iteration, half h = p % 2
+      const int i = p >> 1, h = p & 1, s3 = p >> 2;
+      const int st = j + i;
+      if ((p & 3) == 0) load_b((st >> 1) + 2);
+      if (h == 0) load_a(st + 5, ring[(i + 5) % 6]);  // the set freed by step st - 1
+      __builtin_amdgcn_sched_barrier(0);
+      const int np = p + 1;  // next half-step (np == 12: first of the next iteration, buffer 0)
+      read_b(F[np & 1], (np >> 2) % 3, (np >> 1) & 1, np & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(ring[i], F[p & 1], h);
+      __builtin_amdgcn_sched_barrier(0);
+      if ((p & 3) == 3) {
+        store_b((s3 + 2) % 3);
+        __syncthreads();
       }
-#pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
-          if constexpr (HAS_LO)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-        }
     }
   }
 
-  const float osc = (FMT == MDC_FP16S) ? 1.0f / fscale[f] : 1.0f;
-  // D[i][j] of a 16x16 block: j = lane % 16, i = 4 * (lane / 16) + e
+  // FP16: divide out the kernel's and the spectra's power-of-two scales
+  const float osc = F16 ? 1.0f / (fscale[f] * spec_scale(bmax[f])) : 1.0f;
+  // D of a 32x32 block: column = lane % 32, row = 8 (e / 4) + 4 (lane / 32) + e % 4
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) {
-      const int n = 2 * n0 + wn * 64 + ni * 16 + li;
-      const int v = n >> 1;
+      const int v = n0 + (ni >> 1) * 32 + l32;
       if (v >= ncols) continue;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = m0 + wm * 64 + mi * 16 + 4 * kb + e;
-        if (row < M) Cf[((size_t)row * ncols + v) * 2 + (n & 1)] = acc[mi][ni][e] * osc;
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + wave * 64 + rb * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        if (row < M) Cf[((size_t)row * ncols + v) * 2 + (ni & 1)] = acc[rb][ni][e] * osc;
       }
     }
 }
 
+// Split spectra X[f][k][ncols] (complex FP32) into Bp[f][v][g][8]: words 0-3 the hi pair
+// words (re | im << 16) of k = 4g..4g+3, words 4-7 the lo pair words, v < NCP, g < KG, zero
+// outside [KD) x [ncols).  bf16: hi = RNE(x), lo = RNE(x - hi).  FP16 (F16): the same of
+// x * s_f with s_f = spec_scale(bmax[f]).  One workgroup transposes a 64 (k) x 64 (v) tile
+// through LDS.
+template <bool F16>
+__global__ __launch_bounds__(kThreads) void bsplit_kernel(const float2* __restrict__ X, int KD, int ncols, int KG,
+                                                          int NCP, const float* __restrict__ bmax,
+                                                          unsigned int* __restrict__ Bp) {
+  __shared__ float2 tile[64][65];
+  const int f = blockIdx.z, k0 = blockIdx.x * 64, v0 = blockIdx.y * 64;
+  const float2* Xf = X + (size_t)f * KD * ncols;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int idx = tid + kThreads * i;
+    const int kk = idx >> 6, v = idx & 63;
+    const int k = k0 + kk, c = v0 + v;
+    tile[kk][v] = (k < KD && c < ncols) ? Xf[(size_t)k * ncols + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float sc = F16 ? spec_scale(bmax[f]) : 1.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int task = tid + kThreads * i;
+    const int g = task & 15, v = task >> 4;
+    const int gg = (k0 >> 2) + g;
+    if (gg >= KG) continue;
+    unsigned int hi[4], lo[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      if constexpr (F16) {
+        const float re = tile[4 * g + h][v].x * sc, im = tile[4 * g + h][v].y * sc;
+        const unsigned int hr = f16_rne_bits(re), hm = f16_rne_bits(im);
+        hi[h] = hr | (hm << 16);
+        lo[h] = f16_rne_bits(re - f16_bits_to_f(hr)) | (f16_rne_bits(im - f16_bits_to_f(hm)) << 16);
+      } else {
+        split_pair(tile[4 * g + h][v].x, tile[4 * g + h][v].y, hi[h], lo[h]);
+      }
+    }
+    unsigned int* dst = Bp + (((size_t)f * NCP + v0 + v) * KG + gg) * 8;
+    *reinterpret_cast<u4v*>(dst) = u4v{hi[0], hi[1], hi[2], hi[3]};
+    *reinterpret_cast<u4v*>(dst + 4) = u4v{lo[0], lo[1], lo[2], lo[3]};
+  }
+}
+
+__global__ void zero_floats(float* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// bmax[f] = max |re|, |im| over the spectrum slice of frequency f (bmax zeroed first;
+// the maximum of non-negative floats is order independent, so the atomic is exact).
+__global__ __launch_bounds__(kThreads) void spec_max_kernel(const float2* __restrict__ X, size_t per_f,
+                                                            float* __restrict__ bmax) {
+  __shared__ float part[kThreads / 64];
+  const int f = blockIdx.y;
+  const float2* Xf = X + (size_t)f * per_f;
+  float m = 0.f;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < per_f; i += (size_t)gridDim.x * kThreads) {
+    const float2 z = Xf[i];
+    m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, part[w]);
+    atomicMax(reinterpret_cast<unsigned int*>(bmax) + f, __float_as_uint(m));
+  }
+}
+
+// Bytes of the split spectra: nfmax x (max_cols rounded up to BN) x (reduction rounded up to
+// KSTEP_PAD) x 8.
+size_t split_data_bytes(const mdc_desc& d) {
+  const size_t ncp = (size_t)(d.max_cols + BN - 1) / BN * BN;
+  const size_t kdp = (size_t)((d.ns > d.nr ? d.ns : d.nr) + KSTEP_PAD - 1) / KSTEP_PAD * KSTEP_PAD;
+  return (size_t)d.nfmax * ncp * kdp * 8;
+}
+
 template <int FMT>
 mdc_status launch_fmt(const mdc_desc& d, const char* K, const float* fscale, int ldk, int adjoint, const float2* in,
-                      float2* out, int ncols, hipStream_t st) {
+                      float2* out, int ncols, unsigned int* bsplit, hipStream_t st) {
   const int M = adjoint ? d.nr : d.ns;
+  const int KD = adjoint ? d.ns : d.nr;
   const int tiles_m = (M + BM - 1) / BM;
   const int tiles_n = (ncols + BN - 1) / BN;
+  const int NCP = tiles_n * BN;
+  const int KG = (KD + KSTEP_PAD - 1) / KSTEP_PAD * (KSTEP_PAD / 4);
   const long nb = (long)tiles_m * tiles_n * d.nfmax;
   if (nb > 0x7fffffffL) return fail(MDC_ENOTSUP, "too many GEMM tiles");
   const int nblocks = (int)nb;
+  float* bmax = reinterpret_cast<float*>(reinterpret_cast<char*>(bsplit) + align_up(split_data_bytes(d), 256));
+  const dim3 sgrid((KG * 4 + 63) / 64, NCP / 64, d.nfmax);
+  if constexpr (FMT == MDC_FP16S) {
+    hipLaunchKernelGGL(zero_floats, dim3((d.nfmax + 255) / 256), dim3(256), 0, st, bmax, d.nfmax);
+    const size_t per_f = (size_t)KD * ncols;
+    const int bx = (int)std::min<size_t>(64, (per_f + kThreads * 16 - 1) / (kThreads * 16));
+    hipLaunchKernelGGL(spec_max_kernel, dim3(bx, d.nfmax), dim3(kThreads), 0, st, in, per_f, bmax);
+    hipLaunchKernelGGL(bsplit_kernel<true>, sgrid, dim3(kThreads), 0, st, in, KD, ncols, KG, NCP, bmax, bsplit);
+  } else {
+    hipLaunchKernelGGL(bsplit_kernel<false>, sgrid, dim3(kThreads), 0, st, in, KD, ncols, KG, NCP, bmax, bsplit);
+  }
+  mdc_status s = check_launch("bsplit_kernel");
+  if (s != MDC_OK) return s;
   if (adjoint)
-    hipLaunchKernelGGL((gemm16_kernel<FMT, true>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, d.ns, d.nr, ldk,
-                       in, out, ncols, tiles_m, tiles_n, nblocks);
+    hipLaunchKernelGGL((gemm16_kernel<FMT, true>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, bmax, d.ns, d.nr,
+                       ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks);
   else
-    hipLaunchKernelGGL((gemm16_kernel<FMT, false>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, d.ns, d.nr, ldk,
-                       in, out, ncols, tiles_m, tiles_n, nblocks);
+    hipLaunchKernelGGL((gemm16_kernel<FMT, false>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, bmax, d.ns,
+                       d.nr, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks);
   return check_launch("gemm16_kernel");
 }
 
@@ -295,13 +411,17 @@ mdc_status fp16_scales_launch(float* fscale, int nfmax, hipStream_t st) {
   return check_launch("fp16_scales_kernel");
 }
 
+size_t gemm16_split_bytes(const mdc_desc& d) {
+  return align_up(split_data_bytes(d), 256) + align_up((size_t)d.nfmax * 4, 256);
+}
+
 mdc_status gemm16_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint,
-                         const float2* in, float2* out, int ncols, hipStream_t st) {
+                         const float2* in, float2* out, int ncols, unsigned int* bsplit, hipStream_t st) {
   const char* k = static_cast<const char*>(K);
   switch (d.prec) {
-    case MDC_FP16S: return launch_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
-    case MDC_BF16: return launch_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
-    case MDC_BF16X2: return launch_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+    case MDC_FP16S: return launch_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
+    case MDC_BF16: return launch_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
+    case MDC_BF16X2: return launch_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
     default: return fail(MDC_EINVAL, "gemm16: not a 16-bit format");
   }
 }
