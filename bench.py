@@ -85,7 +85,62 @@ def cpu_baseline(spec, x, y, target_s: float = 8.0):
     return t_full, threads, f"{nsub} of {spec.nfmax} bins (FP64, {reps} repeats), scaled by bins"
 
 
+COPY_BYTES = 256 * 1024 * 1024
+TRAFFIC_COMMANDS = [
+    "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/pmc_fetch "
+    "-o fetch -- python3 $REPO/bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration",
+    "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/pmc_write "
+    "-o write -- python3 $REPO/bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration",
+    "python3 bench.py --write-traffic gpurun_out/pmc_fetch/fetch_results.db gpurun_out/pmc_write/write_results.db",
+]
+
+
+def write_traffic(fetch_db: str, write_db: str) -> None:
+    """Counter-calibrated HBM traffic of the matrix-vector kernels, from two rocprofv3 --pmc runs.
+
+    Each counter (KiB per dispatch) is scaled by bytes / reading of the plain device copies of
+    COPY_BYTES bytes in the same run; the record carries the product source hash so that a
+    changed kernel reports no traffic until the counters are taken again.
+    """
+    import sqlite3
+    import statistics
+
+    def per_kernel(db, counter):
+        out = {}
+        con = sqlite3.connect(db)
+        for name, cn, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+            if cn == counter:
+                short = name.replace("void ", "").replace("mdc::(anonymous namespace)::", "").split("(")[0]
+                out.setdefault(short, []).append(float(v))
+        return out
+
+    fetch, write = per_kernel(fetch_db, "FETCH_SIZE"), per_kernel(write_db, "WRITE_SIZE")
+    copy = "__amd_rocclr_copyBuffer"
+    ff = COPY_BYTES / (statistics.median(sorted(fetch[copy])[-3:]) * 1024)
+    wf = COPY_BYTES / (statistics.median(sorted(write[copy])[-3:]) * 1024)
+    kernels, per_launch = {}, []
+    for name in sorted(fetch):
+        if not name.startswith(("gemv_fwd_kernel", "gemv_adj_kernel")):
+            continue
+        fk, wk = statistics.mean(fetch[name]), statistics.mean(write[name])
+        kernels[name] = {"fetch_KiB_raw": round(fk, 1), "write_KiB_raw": round(wk, 1),
+                         "fetch_bytes": round(fk * 1024 * ff), "write_bytes": round(wk * 1024 * wf)}
+        per_launch.append(fk * 1024 * ff + wk * 1024 * wf)
+    alg = algorithmic_bytes(WORKLOAD["nt"], WORKLOAD["nfmax"], WORKLOAD["nx"] ** 2, WORKLOAD["nv"])[1]
+    rec = {"workload": WORKLOAD, "source": os.path.relpath(PRODUCT_SRC, ROOT),
+           "source_sha256_16": source_hash(PRODUCT_SRC),
+           "copy_calibration": {"bytes_copied": COPY_BYTES, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "kernels": kernels, "bytes_per_launch": round(statistics.mean(per_launch)),
+           "algorithmic_bytes_per_launch": alg,
+           "traffic_over_algorithmic": round(statistics.mean(per_launch) / alg, 4), "commands": TRAFFIC_COMMANDS}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({k: rec[k] for k in ("bytes_per_launch", "traffic_over_algorithmic", "copy_calibration")}))
+
+
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--write-traffic":
+        return write_traffic(sys.argv[2], sys.argv[3])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
