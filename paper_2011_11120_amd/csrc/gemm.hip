@@ -56,7 +56,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
   const int tiles_per_f = tiles_m * tiles_n;
   const int f = L / tiles_per_f;
   const int t = L - f * tiles_per_f;
-  const int mt = t % tiles_m, nt = t / tiles_m;
+  // column tiles of one row block are adjacent, so they run together on one XCD and
+  // share that block's kernel rows through L2 instead of each reading them from HBM
+  const int nt = t % tiles_n, mt = t / tiles_n;
   const int M = ADJ ? nr : ns;
   const int KD = ADJ ? ns : nr;
   const int m0 = mt * BM, n0 = nt * BN;

@@ -109,7 +109,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
   const int tiles_per_f = tiles_m * tiles_n;
   const int f = L / tiles_per_f;
   const int t = L - f * tiles_per_f;
-  const int mt = t % tiles_m, nt = t / tiles_m;
+  // column tiles of one row block are adjacent, so they run together on one XCD and
+  // share that block's kernel rows through L2 instead of each reading them from HBM
+  const int nt = t % tiles_n, mt = t / tiles_n;
   const int m0 = mt * BM, n0 = nt * BN;
   const int M = ADJ ? nr : ns;
   const size_t rowb = X2 ? (size_t)ldk * 8 : (size_t)ldk * 4;
