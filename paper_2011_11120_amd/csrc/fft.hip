@@ -116,6 +116,15 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* tws, int tid)
   }
 }
 
+// Workgroup number with neighbouring trace groups on the same XCD (hardware deals
+// workgroups round-robin over the 8 XCDs): two neighbours share 128-byte lines of
+// every time row, which one L2 then fetches and writes back once.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q8 = nb >> 3, rem = nb & 7, xcd = b & 7;
+  return xcd * q8 + min(xcd, rem) + (b >> 3);
+}
+
 template <int M>
 __device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __restrict__ tw, int tid) {
   for (int k = tid; k < 2 * M; k += kThreads) tws[k] = tw[k];
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
   constexpr int NT = 2 * M;
   const int Q = n * nv;
   const int tid = threadIdx.x;
-  const int q0 = blockIdx.x * CB;
+  const int q0 = xcd_block() * CB;
   stage_twiddles<M>(tws, tw, tid);
 
   if constexpr (VEC) {
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   constexpr int NT = 2 * M;
   const int Q = n * nv;
   const int tid = threadIdx.x;
-  const int q0 = blockIdx.x * CB;
+  const int q0 = xcd_block() * CB;
   stage_twiddles<M>(tws, tw, tid);
   __syncthreads();
 
