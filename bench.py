@@ -455,12 +455,14 @@ def bench_c5(args):
             t0 = time.perf_counter()
             lat, kept = serve_run(srv, reqs, rate=rate if mode == "poisson" else None, keep=(0, 1))
             st = srv.stats(skip=0)
+            gs = srv.graph_stats()
             srv.close()
             srv = mdc.Server(op, 100, dx=spec.dx, dt=spec.dt, arena=arena_t)
             l = np.array([lat[k] for k in sorted(lat)])[args.skip:]
             res[mode] = {"solves_per_s": round(len(lat) / (time.perf_counter() - t0), 4),
                          "p50_s": round(float(np.percentile(l, 50)), 3), "p99_s": round(float(np.percentile(l, 99)), 3),
-                         "max_active": st["max_active"], "steps": st["steps"]}
+                         "max_active": st["max_active"], "steps": st["steps"],
+                         "graph_steps": {"captured": gs["captured"], "replayed": gs["replayed"]}}
             if mode == "closed":
                 sols[prec] = kept
                 if rate is None:

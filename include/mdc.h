@@ -299,6 +299,12 @@ mdc_status serve_drain(mdc_server* srv);
 mdc_status serve_stats(mdc_server* srv, int skip, double* solves_per_s, double* p50_s, double* p99_s,
                        int* completed, int* max_active, long* steps);
 /* Stop the worker (cancelling what is left) and release the handle. */
+/* Steps captured into hipGraphs and steps replayed from them so far.  Within a fixed set
+ * of active requests every forward and every adjoint step enqueues the same launches: the
+ * first step of such a composition runs eagerly, the second is captured, later ones replay
+ * the graph (environment MDC_SERVE_GRAPH=0 runs every step eagerly). */
+mdc_status serve_graph_stats(mdc_server* srv, long* captured, long* replayed);
+
 mdc_status serve_destroy(mdc_server* srv);
 
 #ifdef __cplusplus

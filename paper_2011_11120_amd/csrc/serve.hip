@@ -23,9 +23,11 @@
 // have zero inputs, zero window, a zero keep mask on adjoint outputs, and R is
 // scaled by d (areal element d dx^2), which equals the decimated problem.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -187,6 +189,13 @@ struct mdc_server {
   long steps = 0;
   bool forward_next = true;
   mdc_status error = MDC_OK;
+  // Steps replayed from captured graphs, keyed by direction and the (request, phase) list:
+  // within a fixed set of active requests every forward and every adjoint step enqueues the
+  // same launches.  A key's first step runs eagerly, its second is captured.
+  std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+  std::map<std::vector<uint64_t>, int> seen;
+  bool graphs_ok = true;
+  std::atomic<long> captured{0}, replayed{0};
 };
 
 namespace {
@@ -195,12 +204,12 @@ int cols_for(const Request* r) { return r->phase == kData ? r->nv : 2 * r->nv; }
 
 bool wants_forward(const Request* r) { return r->phase == kData || r->phase == kIterF; }
 
-// Enqueue one fused step for the requests in `part` (all in the same direction).
-mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
+// Enqueue one fused step for the requests in `part` (all in the same direction).  Only
+// launches: the phase transitions are applied afterwards by advance().
+mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hipStream_t st) {
   mdc_op* op = S->op;
   const mdc_desc& d = op->d;
   const int n = d.ns;
-  hipStream_t st = S->stream;
   int N = 0;
   for (Request* r : part) {
     r->c0 = N;
@@ -235,31 +244,91 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, st, r->S.u + half, half);
       lsqr_after_b(r->S, st);
-      r->phase = kInitAdj;
     } else if (fwd) {  // t0 = v0 - d Theta R v1 ; t1 = v1 - d Theta R* v0
       IfftSeg a{r->S.t, r->S.v, r->onset, 0, r->c0, -dsc};
       IfftSeg b{r->S.t + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc};
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
       lsqr_after_fwd(r->S, st);
-      r->phase = kIterA;
     } else {  // t2_1 = u1 - d keep R^H Theta u0 ; t2_0 = u0 - d keep R*^H Theta u1
       const int* km = r->decim > 1 ? r->keep : nullptr;
       IfftSeg a{r->S.t2 + half, r->S.u + half, km, 0, r->c0, -dsc};
       IfftSeg b{r->S.t2, r->S.u, km, 1, r->c0 + r->nv, -dsc};
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
-      if (r->phase == kInitAdj) {
-        lsqr_after_init_adj(r->S, st);
-        r->phase = r->niter > 0 ? kIterF : kDone;
-      } else {
-        r->it += 1;
-        lsqr_after_adj(r->S, st);
-        r->phase = r->it >= r->niter ? kDone : kIterF;
-      }
+      if (r->phase == kInitAdj) lsqr_after_init_adj(r->S, st);
+      else lsqr_after_adj(r->S, st);
     }
   }
   return check_launch("serve step");
+}
+
+// Phase transitions of the requests of a step that has been enqueued.
+void advance(std::vector<Request*>& part, bool fwd) {
+  for (Request* r : part) {
+    if (r->phase == kData) {
+      r->phase = kInitAdj;
+    } else if (fwd) {
+      r->phase = kIterA;
+    } else if (r->phase == kInitAdj) {
+      r->phase = r->niter > 0 ? kIterF : kDone;
+    } else {
+      r->it += 1;
+      r->phase = r->it >= r->niter ? kDone : kIterF;
+    }
+  }
+}
+
+void drop_graphs(mdc_server* S) {
+  for (auto& kv : S->graphs) hipGraphExecDestroy(kv.second);
+  S->graphs.clear();
+}
+
+// One step: replayed from its captured graph when this composition has run before.
+mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
+  hipStream_t st = S->stream;
+  const char* g = getenv("MDC_SERVE_GRAPH");
+  const bool use = S->graphs_ok && !S->op->prof && !(g && g[0] == '0');
+  mdc_status s = MDC_OK;
+  if (!use) {
+    s = enqueue_step(S, part, fwd, st);
+  } else {
+    std::vector<uint64_t> key{fwd ? 1ull : 0ull};
+    for (Request* r : part) {
+      key.push_back(r->id);
+      key.push_back((uint64_t)r->phase);
+    }
+    auto hit = S->graphs.find(key);
+    if (hit != S->graphs.end()) {
+      S->replayed += 1;
+      if (hipGraphLaunch(hit->second, st) != hipSuccess) s = fail(MDC_EDEVICE, "hipGraphLaunch failed");
+    } else if (S->seen[key]++ == 0) {  // first occurrence: eager (initialises every kernel variant)
+      s = enqueue_step(S, part, fwd, st);
+    } else {
+      if (S->graphs.size() >= 32) drop_graphs(S);  // compositions come and go; keep the cache small
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        const mdc_status cs = enqueue_step(S, part, fwd, st);
+        ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph != nullptr && cs == MDC_OK;
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) hipGraphDestroy(graph);
+      }
+      if (ok) {
+        S->graphs[key] = exec;
+        S->captured += 1;
+        if (hipGraphLaunch(exec, st) != hipSuccess) s = fail(MDC_EDEVICE, "hipGraphLaunch failed");
+      } else {  // capture unavailable: run eagerly from now on (nothing of the capture executed)
+        hipGetLastError();
+        S->graphs_ok = false;
+        s = enqueue_step(S, part, fwd, st);
+      }
+    }
+    if (S->seen.size() > 4096) S->seen.clear();
+  }
+  advance(part, fwd);
+  return s;
 }
 
 // Give a request its arena slot and generate its inputs (called with the lock held).
@@ -515,6 +584,13 @@ mdc_status serve_stats(mdc_server* S, int skip, double* solves_per_s, double* p5
   return MDC_OK;
 }
 
+mdc_status serve_graph_stats(mdc_server* S, long* captured, long* replayed) {
+  if (!S) return fail(MDC_EINVAL, "NULL server");
+  if (captured) *captured = S->captured.load();
+  if (replayed) *replayed = S->replayed.load();
+  return MDC_OK;
+}
+
 mdc_status serve_destroy(mdc_server* S) {
   if (!S) return MDC_OK;
   {
@@ -524,6 +600,7 @@ mdc_status serve_destroy(mdc_server* S) {
   S->cv.notify_all();
   if (S->worker.joinable()) S->worker.join();
   hipStreamSynchronize(S->stream);
+  drop_graphs(S);
   hipStreamDestroy(S->stream);
   for (auto& kv : S->all) delete kv.second;
   delete S;

@@ -96,6 +96,7 @@ def _load():
         "serve_drain": (st, [vp]),
         "serve_stats": (st, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_long)]),
+        "serve_graph_stats": (st, [vp, C.POINTER(C.c_long), C.POINTER(C.c_long)]),
         "serve_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -112,7 +113,7 @@ EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", 
            "lsqr_query_sizes", "lsqr_solve", "cgls_solve", "mdc_set_kernel_time", "mch_greens",
            "mch_neumann_query", "mch_neumann",
            "serve_request_bytes", "serve_create", "serve_submit", "serve_poll", "serve_cancel", "serve_drain",
-           "serve_stats", "serve_destroy")
+           "serve_stats", "serve_graph_stats", "serve_destroy")
 
 
 def _check(status: int):
@@ -303,6 +304,12 @@ def serve_stats(srv, skip=0):
             "max_active": mact.value, "steps": steps.value}
 
 
+def serve_graph_stats(srv):
+    cap, rep = C.c_long(), C.c_long()
+    _check(_lib.serve_graph_stats(srv, C.byref(cap), C.byref(rep)))
+    return {"captured": cap.value, "replayed": rep.value}
+
+
 def serve_destroy(srv):
     _check(_lib.serve_destroy(srv))
 
@@ -346,6 +353,9 @@ class Server:
 
     def stats(self, skip=0):
         return serve_stats(self.handle, skip)
+
+    def graph_stats(self):
+        return serve_graph_stats(self.handle)
 
     def close(self):
         if self.handle is not None:

@@ -144,3 +144,34 @@ def test_cancel_leaves_others_intact(mdcmod, served):
     idx, xr, _ = oracle_solution(kap, 1, *keep_pts, 4)
     assert rel2(x[:, :, idx], xr) < 1e-5
     srv.close()
+
+
+def test_graph_replayed_steps_match_eager_steps(mdcmod, served, monkeypatch):
+    """Steps replayed from captured hipGraphs give the results of eagerly launched steps."""
+    op, kap = served
+
+    def run():
+        srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+        # iteration counts close together, so each composition of active requests lasts
+        # several steps (a composition is captured on its second step, replayed after)
+        mix = [(1, 9, 1), (3, 9, 1), (2, 10, 2), (5, 9, 4), (1, 10, 2), (4, 9, 1)]
+        reqs = [(nv, niter, decim, *points(nv, 70 + k)) for k, (nv, niter, decim) in enumerate(mix)]
+        ids = [srv.submit(vx, vy, vz, niter, decim) for nv, niter, decim, vx, vy, vz in reqs]
+        srv.drain()
+        out = [tuple(t.clone() for t in srv.result(i)) for i in ids]
+        gs = srv.graph_stats()
+        srv.close()
+        return reqs, out, gs
+
+    monkeypatch.setenv("MDC_SERVE_GRAPH", "0")
+    _, eager, gs0 = run()
+    assert gs0["replayed"] == 0 and gs0["captured"] == 0
+    monkeypatch.delenv("MDC_SERVE_GRAPH")
+    reqs, graphed, gs1 = run()
+    print(f"graph stats {gs1}", flush=True)
+    assert gs1["captured"] > 0 and gs1["replayed"] > gs1["captured"]
+    for (nv, niter, decim, vx, vy, vz), (xe, he), (xg, hg) in zip(reqs, eager, graphed):
+        # step compositions may differ between runs (admission timing), hence the tolerance
+        assert rel2(xg.cpu().numpy(), xe.cpu().numpy()) < 1e-5
+        idx, xr, hr = oracle_solution(kap, decim, vx, vy, vz, niter)
+        assert rel2(xg.cpu().numpy().astype(np.float64)[:, :, idx], xr) < 1e-5
