@@ -366,11 +366,14 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   }
 }
 
-// Columns per workgroup: wide blocks when there are many traces, narrow ones
-// (more workgroups) when there are few.
-template <int M>
+// Wide width: 16 traces, or 8 where a wide tile would leave too few workgroups per CU
+// (forward M >= 1024; inverse M >= 512, whose 8-trace tiles measured faster).
+template <int M, bool INV>
+constexpr int wide_cb() { return (M >= (INV ? 512 : 1024)) ? 8 : 16; }
+
+template <int M, bool INV>
 int pick_cb(int Q) {
-  const int maxcb = (M >= 1024) ? 8 : 16;
+  constexpr int maxcb = wide_cb<M, INV>();
   if (Q >= 256 * 2 * maxcb) return maxcb;
   return 4;
 }
@@ -409,8 +412,8 @@ mdc_status rfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const Ff
 template <int M>
 mdc_status rfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const FftSeg& s, float2* spec,
                     hipStream_t st) {
-  constexpr int WIDE = (M >= 1024) ? 8 : 16;
-  if (pick_cb<M>(n * nv) == WIDE) return rfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
+  constexpr int WIDE = wide_cb<M, false>();
+  if (pick_cb<M, false>(n * nv) == WIDE) return rfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
   return rfft_cb<M, 4>(tw, nfmax, n, nv, ldc, s, spec, st);
 }
 
@@ -448,8 +451,8 @@ mdc_status irfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const I
 template <int M>
 mdc_status irfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const IfftSeg& s, const float2* spec,
                      hipStream_t st) {
-  constexpr int WIDE = (M >= 1024) ? 8 : 16;
-  if (pick_cb<M>(n * nv) == WIDE) return irfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
+  constexpr int WIDE = wide_cb<M, true>();
+  if (pick_cb<M, true>(n * nv) == WIDE) return irfft_cb<M, WIDE>(tw, nfmax, n, nv, ldc, s, spec, st);
   return irfft_cb<M, 4>(tw, nfmax, n, nv, ldc, s, spec, st);
 }
 
