@@ -193,7 +193,7 @@ mdc_status check_vec(const void* p, const char* name) {
 // pre: optional window [nr][nv] on the model side (a time-domain preconditioner P, so the
 // operator is C P, adjoint P C^H), or nullptr.
 mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st,
-                       const int* pre = nullptr) {
+                       const int* pre = nullptr, const double* in_scale = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
   if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
@@ -206,7 +206,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   float2* spec_out = adjoint ? op->specR : op->specS;
   {
     Stage t(op, 0, st);
-    FftSeg seg{in, adjoint ? nullptr : pre, 0, 0};
+    FftSeg seg{in, adjoint ? nullptr : pre, 0, 0, in_scale};
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, nin, nv, nv, seg, spec_in, st)) != MDC_OK) return s;
   }
   {
@@ -223,7 +223,8 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
 
 // Marchenko block operator (Eq.5): one kernel pass with columns [block for R | conj block for R*].
 mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
-                           float* out1, int adjoint, hipStream_t st, int mode = 0) {
+                           float* out1, int adjoint, hipStream_t st, int mode = 0,
+                           const double* in_scale = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
   if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
@@ -241,8 +242,8 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     Stage t(op, 0, st);
     // forward: R acts on in1, R* on in0; adjoint: R^H on Theta in0, R*^H on Theta in1
     const int* pre = adjoint ? onset : nullptr;
-    FftSeg a{adjoint ? in0 : in1, pre, 0, 0};
-    FftSeg b{adjoint ? in1 : in0, pre, 1, nv};
+    FftSeg a{adjoint ? in0 : in1, pre, 0, 0, in_scale};
+    FftSeg b{adjoint ? in1 : in0, pre, 1, nv, in_scale};
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_in, st)) != MDC_OK) return s;
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_in, st)) != MDC_OK) return s;
   }
@@ -257,8 +258,8 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     // adjoint: out1 = in1 - R^H Theta in0 (cols 0..nv), out0 = in0 - R*^H Theta in1 (cols nv..2nv, conj)
     // mode 1 (Neumann term B = I - M): no identity blocks, + sign
     const float sg = mode == 1 ? 1.0f : -1.0f;
-    IfftSeg a{adjoint ? out1 : out0, mode == 1 ? nullptr : (adjoint ? in1 : in0), post, 0, 0, sg};
-    IfftSeg b{adjoint ? out0 : out1, mode == 1 ? nullptr : (adjoint ? in0 : in1), post, 1, nv, sg};
+    IfftSeg a{adjoint ? out1 : out0, mode == 1 ? nullptr : (adjoint ? in1 : in0), post, 0, 0, sg, 1.0f, in_scale};
+    IfftSeg b{adjoint ? out0 : out1, mode == 1 ? nullptr : (adjoint ? in0 : in1), post, 1, nv, sg, 1.0f, in_scale};
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_out, st)) != MDC_OK) return s;
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_out, st)) != MDC_OK) return s;
   }
@@ -408,13 +409,14 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
 mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
                     void* work, hipStream_t st);
 
-// One application of the solver's operator (MDC or Marchenko); Marchenko vectors are two
-// contiguous blocks of `half` elements.
+// One application of the solver's operator (MDC or Marchenko) to in_scale * in (in_scale a
+// device scalar, or nullptr for 1); Marchenko vectors are two contiguous blocks of `half`
+// elements.
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st) {
+                    size_t half, hipStream_t st, const double* in_scale) {
   if (kind == MDC_OP_MARCHENKO)
-    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st);
-  return apply_plain(op, in, out, nv, adjoint, st, onset);
+    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st, 0, in_scale);
+  return apply_plain(op, in, out, nv, adjoint, st, onset, in_scale);
 }
 }  // namespace mdc
 

@@ -82,6 +82,7 @@ struct FftSeg {
   const int* onset;    // optional pre-window [n][nv] (adjoint Marchenko), or nullptr
   int conj;            // conjugate the spectrum
   int c0;              // first spectral column
+  const double* dscale = nullptr;  // optional device scalar multiplying the input as it is read
 };
 struct IfftSeg {
   float* out;          // time-domain output [nt][n][nv]
@@ -91,6 +92,7 @@ struct IfftSeg {
   int c0;              // first spectral column
   float sign;          // multiplier of the transformed term
   float ident_scale = 1.0f;
+  const double* ident_dscale = nullptr;  // optional device scalar multiplying ident as it is read
 };
 
 // FFT tables in the resident buffer: tw[k] = exp(-2 pi i k / nt), k < nt.
@@ -113,6 +115,10 @@ struct LsqrState {
   size_t model, data;          // element counts
 };
 size_t lsqr_scalars_bytes();
+// Device scalars 1/beta and 1/alpha: u and v are kept unnormalised and every consumer scales
+// them as it reads them (no separate normalisation pass).
+const double* lsqr_uinv(const LsqrState& s);
+const double* lsqr_vinv(const LsqrState& s);
 void lsqr_after_b(const LsqrState& s, hipStream_t st);
 void lsqr_after_init_adj(const LsqrState& s, hipStream_t st);
 void lsqr_after_fwd(const LsqrState& s, hipStream_t st);

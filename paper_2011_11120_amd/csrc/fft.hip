@@ -138,7 +138,8 @@ __device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __rest
 template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
     const float* __restrict__ x, const int* __restrict__ onset, int conj, const float2* __restrict__ tw,
-    int nfmax, int n, int nv, int ldc, int c0, float scale, float2* __restrict__ spec) {
+    int nfmax, int n, int nv, int ldc, int c0, float scale, float2* __restrict__ spec,
+    const double* __restrict__ dscale) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
   float2* lds = sh;            // [M][CB]
   float2* tws = sh + M * CB;   // [2M]
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
   const int tid = threadIdx.x;
   const int q0 = xcd_block() * CB;
   stage_twiddles<M>(tws, tw, tid);
+  const float ds = dscale != nullptr ? (float)*dscale : 1.0f;
 
   if constexpr (VEC) {
     constexpr int CG = CB / 4;                 // 4-trace groups per row
@@ -170,8 +172,8 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
       if (task >= TASKS) continue;
       const int m = task / CG, g = task - (task / CG) * CG;
       const int q = q0 + 4 * g;
-      float a[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
-      float b[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+      float a[4] = {ra[i].x * ds, ra[i].y * ds, ra[i].z * ds, ra[i].w * ds};
+      float b[4] = {rb[i].x * ds, rb[i].y * ds, rb[i].z * ds, rb[i].w * ds};
       if (onset != nullptr && q < Q) {
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void rfft_trunc_kernel(
     for (int i = 0; i < TPT; ++i) {
       const int m = tid / CB + i * ROWS;
       if (m >= M) continue;
-      float a = ra[i], b = rb[i];
+      float a = ra[i] * ds, b = rb[i] * ds;
       if (!in_window(2 * m, NT, on)) a = 0.f;
       if (!in_window(2 * m + 1, NT, on)) b = 0.f;
       lds[m * CB + col] = make_float2(a, b);
@@ -257,7 +259,7 @@ template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
     const float2* __restrict__ spec, int ldc, int c0, int conj, const float2* __restrict__ tw, int nfmax,
     int n, int nv, float scale, float* out, const float* ident,
-    const int* __restrict__ onset, float sign, float iscale) {
+    const int* __restrict__ onset, float sign, float iscale0, const double* __restrict__ ident_dscale) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
   float2* lds = sh;
   float2* tws = sh + M * CB;
@@ -266,6 +268,7 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   const int tid = threadIdx.x;
   const int q0 = xcd_block() * CB;
   stage_twiddles<M>(tws, tw, tid);
+  const float iscale = ident_dscale != nullptr ? iscale0 * (float)*ident_dscale : iscale0;
   __syncthreads();
 
   auto bin2 = [&](int k, int q, float2& X0, float2& X1) {
@@ -391,7 +394,7 @@ mdc_status rfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const F
     attr = true;
   }
   hipLaunchKernelGGL((rfft_trunc_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, s.in,
-                     s.onset, s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec);
+                     s.onset, s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec, s.dscale);
   return check_launch("rfft_trunc_kernel");
 }
 
@@ -430,7 +433,8 @@ mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const 
     attr = true;
   }
   hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, spec,
-                     ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign, s.ident_scale);
+                     ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign, s.ident_scale,
+                     s.ident_dscale);
   return check_launch("irfft_pad_kernel");
 }
 

@@ -16,7 +16,7 @@
 namespace mdc {
 
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st);
+                    size_t half, hipStream_t st, const double* in_scale = nullptr);
 
 namespace {
 
@@ -27,6 +27,7 @@ struct Scalars {
   double alpha, beta, rhobar, phibar;
   double cx, cw;        // x += cx w ; w = v + cw w
   double inv;           // reciprocal of the last norm (or 1 when it was 0)
+  double uinv, vinv;    // 1/beta, 1/alpha: u and v are stored unnormalised (beta u, alpha v)
   int iter, pad;        // completed iterations (device-side, so every iteration's launches are identical)
   double gamma, qn, sn, rn;  // CGLS: ||s||^2 of the last step, last norms of q, s, r
   double part[kParts];  // stage-1 partial sums
@@ -44,11 +45,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in thread 0
 }
 
-// out = a * x + coef * y  (coef = sgn * *cptr, or sgn when cptr is NULL); partial sum of out^2
-__global__ __launch_bounds__(kThreads) void lin_norm(float* out, const float* x, const float* y, const double* __restrict__ cptr,
+// out = x + coef * y  (coef = sgn * (*c1 or 1) * (*c2 or 1)); partial sum of out^2
+__global__ __launch_bounds__(kThreads) void lin_norm(float* out, const float* x, const float* y,
+                                                     const double* __restrict__ c1, const double* __restrict__ c2,
                                                      double sgn, size_t n, Scalars* sc) {
   __shared__ double sh[kThreads / 64];
-  const float coef = (float)(cptr ? sgn * *cptr : sgn);
+  const float coef = (float)(sgn * (c1 ? *c1 : 1.0) * (c2 ? *c2 : 1.0));
   double acc = 0.0;
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
     const float v = x[i] + coef * y[i];
@@ -69,8 +71,8 @@ __global__ __launch_bounds__(kThreads) void sumsq(const float* __restrict__ x, s
   if (threadIdx.x == 0) sc->part[blockIdx.x] = t;
 }
 
-// norm = sqrt(sum of partials) into *dst; sc->inv = 1/norm (1 if norm == 0)
-__global__ __launch_bounds__(kThreads) void finish_norm(Scalars* sc, double* dst, int nparts) {
+// norm = sqrt(sum of partials) into *dst; *inv = 1/norm (1 if norm == 0)
+__global__ __launch_bounds__(kThreads) void finish_norm(Scalars* sc, double* dst, double* inv, int nparts) {
   __shared__ double sh[kThreads / 64];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kThreads) acc += sc->part[i];
@@ -78,22 +80,18 @@ __global__ __launch_bounds__(kThreads) void finish_norm(Scalars* sc, double* dst
   if (threadIdx.x == 0) {
     const double nrm = sqrt(t);
     *dst = nrm;
-    sc->inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+    *inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void scale_inv(float* __restrict__ x, size_t n, const Scalars* sc) {
-  const float s = (float)sc->inv;
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) x[i] *= s;
-}
-
-// w = v, x = 0, phibar = beta, rhobar = alpha
+// w = v (= vinv * stored v), x = 0, phibar = beta, rhobar = alpha
 __global__ __launch_bounds__(kThreads) void init_xw(float* __restrict__ x, float* __restrict__ w,
                                                     const float* __restrict__ v, size_t n, Scalars* sc,
                                                     double* hist) {
+  const float vi = (float)sc->vinv;
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
     x[i] = 0.f;
-    w[i] = v[i];
+    w[i] = v[i] * vi;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->phibar = sc->beta;
@@ -124,14 +122,14 @@ __global__ void givens(Scalars* sc, double* hist) {
   if (hist) hist[it] = sc->phibar;
 }
 
-// x += cx w ; w = v + cw w
+// x += cx w ; w = v + cw w  (v = vinv * stored v)
 __global__ __launch_bounds__(kThreads) void update_xw(float* __restrict__ x, float* __restrict__ w,
                                                       const float* __restrict__ v, size_t n, const Scalars* sc) {
-  const float cx = (float)sc->cx, cw = (float)sc->cw;
+  const float cx = (float)sc->cx, cw = (float)sc->cw, vi = (float)sc->vinv;
   for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads) {
     const float wi = w[i];
     x[i] += cx * wi;
-    w[i] = v[i] + cw * wi;
+    w[i] = v[i] * vi + cw * wi;
   }
 }
 
@@ -179,42 +177,48 @@ inline int grid_for(size_t n) {
 
 size_t lsqr_scalars_bytes() { return align_up(sizeof(Scalars), 256); }
 
-// beta u = u (u holds b on entry)
+const double* lsqr_uinv(const LsqrState& s) { return &static_cast<Scalars*>(s.sc)->uinv; }
+const double* lsqr_vinv(const LsqrState& s) { return &static_cast<Scalars*>(s.sc)->vinv; }
+
+// The Paige-Saunders recurrences with u and v stored unnormalised: the stored u is
+// beta u and the stored v is alpha v; uinv = 1/beta and vinv = 1/alpha are applied by
+// every consumer as it reads them (the operator's input transform and identity terms,
+// the next recurrence, the w update), which saves a read-write pass over each vector.
+
+// beta u = b (u holds b on entry)
 void lsqr_after_b(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gd = grid_for(s.data);
   hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
-  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, &sc->uinv, gd);
 }
 
 // alpha v = t2 (= A^H u), w = v, x = 0
 void lsqr_after_init_adj(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gm = grid_for(s.model);
-  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.t2, (const double*)nullptr, 0.0,
-                     s.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
-  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, s.v, s.model, sc);
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.t2, (const double*)nullptr,
+                     (const double*)nullptr, 0.0, s.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, &sc->vinv, gm);
   hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc, s.hist);
 }
 
-// beta u = t - alpha u  (t = A v)
+// beta u = t - alpha u  (t = A v; the stored previous u times uinv is u)
 void lsqr_after_fwd(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gd = grid_for(s.data);
-  hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, s.u, s.t, s.u, &sc->alpha, -1.0, s.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, gd);
-  hipLaunchKernelGGL(scale_inv, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
+  hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, s.u, s.t, s.u, (const double*)&sc->alpha,
+                     (const double*)&sc->uinv, -1.0, s.data, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, &sc->uinv, gd);
 }
 
 // alpha v = t2 - beta v  (t2 = A^H u); rotation; x += phi/rho w; w = v - theta/rho w
 void lsqr_after_adj(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gm = grid_for(s.model);
-  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.v, &sc->beta, -1.0, s.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, gm);
-  hipLaunchKernelGGL(scale_inv, dim3(gm), dim3(kThreads), 0, st, s.v, s.model, sc);
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.v, (const double*)&sc->beta,
+                     (const double*)&sc->vinv, -1.0, s.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, &sc->vinv, gm);
   hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
   hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
 }
@@ -292,14 +296,14 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
 
   hipLaunchKernelGGL(copy_f32, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.u, b, z.data);
   lsqr_after_b(S, st);
-  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st)) != MDC_OK) return s;
+  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st, lsqr_uinv(S))) != MDC_OK) return s;
   lsqr_after_init_adj(S, st);
   if ((s = check_launch("lsqr init")) != MDC_OK) return s;
   auto iteration = [&](hipStream_t q) -> mdc_status {
     mdc_status e;
-    if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q)) != MDC_OK) return e;
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q, lsqr_vinv(S))) != MDC_OK) return e;
     lsqr_after_fwd(S, q);
-    if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q)) != MDC_OK) return e;
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q, lsqr_uinv(S))) != MDC_OK) return e;
     lsqr_after_adj(S, q);
     return check_launch("lsqr iteration");
   };
@@ -363,27 +367,27 @@ mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   // r = b ; s = A^H r ; p = s ; x = 0
   hipLaunchKernelGGL(copy_f32, dim3(gd), dim3(kThreads), 0, st, r, b, z.data);
   hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, gd);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, &sc->inv, gd);
   if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
-  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, sv, (const double*)nullptr, 0.0, z.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, gm);
+  hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, sv, (const double*)nullptr, (const double*)nullptr, 0.0, z.model, sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, &sc->inv, gm);
   hipLaunchKernelGGL(zero_vec, dim3(gm), dim3(kThreads), 0, st, x, z.model);
   hipLaunchKernelGGL(cg_init, dim3(1), dim3(64), 0, st, sc, hist);
   for (int it = 1; it <= ld.niter; ++it) {
     // q = A p ; alpha = gamma / ||q||^2 ; x += alpha p ; r -= alpha q
     if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 0, p, q, half, st)) != MDC_OK) return s;
     hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, q, z.data, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->qn, gd);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->qn, &sc->inv, gd);
     hipLaunchKernelGGL(cg_alpha, dim3(1), dim3(64), 0, st, sc);
     hipLaunchKernelGGL(cg_xr, dim3(gx), dim3(kThreads), 0, st, x, p, r, q, z.model, z.data, sc);
     hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, gd);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, &sc->inv, gd);
     // s = A^H r ; beta = ||s||^2 / gamma ; p = s + beta p
     if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
     hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, sv, z.model, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, gm);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, &sc->inv, gm);
     hipLaunchKernelGGL(cg_beta, dim3(1), dim3(64), 0, st, sc, hist);
-    hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, p, &sc->beta, 1.0, z.model, sc);
+    hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, p, (const double*)&sc->beta, (const double*)nullptr, 1.0, z.model, sc);
     if ((s = check_launch("cgls iteration")) != MDC_OK) return s;
   }
   return MDC_OK;

@@ -223,14 +223,14 @@ mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hi
     if (r->phase == kData) {
       FftSeg a{r->S.w, nullptr, 0, r->c0};  // fd was generated into w (block 0)
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
-    } else if (fwd) {  // R on v1, R* on v0
-      FftSeg a{r->S.v + half, nullptr, 0, r->c0};
-      FftSeg b{r->S.v, nullptr, 1, r->c0 + r->nv};
+    } else if (fwd) {  // R on v1, R* on v0 (stored v times 1/alpha)
+      FftSeg a{r->S.v + half, nullptr, 0, r->c0, lsqr_vinv(r->S)};
+      FftSeg b{r->S.v, nullptr, 1, r->c0 + r->nv, lsqr_vinv(r->S)};
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
-    } else {  // R^H on Theta u0, R*^H on Theta u1
-      FftSeg a{r->S.u, r->onset, 0, r->c0};
-      FftSeg b{r->S.u + half, r->onset, 1, r->c0 + r->nv};
+    } else {  // R^H on Theta u0, R*^H on Theta u1 (stored u times 1/beta)
+      FftSeg a{r->S.u, r->onset, 0, r->c0, lsqr_uinv(r->S)};
+      FftSeg b{r->S.u + half, r->onset, 1, r->c0 + r->nv, lsqr_uinv(r->S)};
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
     }
@@ -245,15 +245,15 @@ mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hi
       hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, st, r->S.u + half, half);
       lsqr_after_b(r->S, st);
     } else if (fwd) {  // t0 = v0 - d Theta R v1 ; t1 = v1 - d Theta R* v0
-      IfftSeg a{r->S.t, r->S.v, r->onset, 0, r->c0, -dsc};
-      IfftSeg b{r->S.t + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc};
+      IfftSeg a{r->S.t, r->S.v, r->onset, 0, r->c0, -dsc, 1.0f, lsqr_vinv(r->S)};
+      IfftSeg b{r->S.t + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_vinv(r->S)};
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
       lsqr_after_fwd(r->S, st);
     } else {  // t2_1 = u1 - d keep R^H Theta u0 ; t2_0 = u0 - d keep R*^H Theta u1
       const int* km = r->decim > 1 ? r->keep : nullptr;
-      IfftSeg a{r->S.t2 + half, r->S.u + half, km, 0, r->c0, -dsc};
-      IfftSeg b{r->S.t2, r->S.u, km, 1, r->c0 + r->nv, -dsc};
+      IfftSeg a{r->S.t2 + half, r->S.u + half, km, 0, r->c0, -dsc, 1.0f, lsqr_uinv(r->S)};
+      IfftSeg b{r->S.t2, r->S.u, km, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_uinv(r->S)};
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
       if (r->phase == kInitAdj) lsqr_after_init_adj(r->S, st);
