@@ -3,7 +3,7 @@
 // orthogonal real transform, 1/sqrt(nt) both ways, positive frequencies only).
 //
 // A length-nt real trace is packed into M = nt/2 complex points
-// z[m] = x[2m] + i x[2m+1] and transformed by a radix-4 (plus one radix-2)
+// z[m] = x[2m] + i x[2m+1] and transformed by a radix-8 (plus one radix-2 or 4)
 // Stockham FFT held in LDS; a split step then yields the nt/2+1 real-signal
 // bins, of which only the first nfmax are written.  The inverse runs the same
 // steps backwards from zero-padded bins, dropping the imaginary parts of the
@@ -44,76 +44,101 @@ __device__ __forceinline__ void bfly4(float2& a0, float2& a1, float2& a2, float2
   a3 = csub(t1, id);
 }
 
-// Complete M-point Stockham FFT (unnormalised) of the CB columns in lds[M][CB].
-// tws: twiddle table in LDS (nt = 2M entries).
+// y = DFT_8(v) with sign DIR, in place: two DFT_4 of the even and odd points and one
+// radix-2 combination with w8^k = exp(DIR 2 pi i k / 8).
+template <int DIR>
+__device__ __forceinline__ void bfly8(float2 (&v)[8]) {
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  bfly4<DIR>(e0, e1, e2, e3);
+  bfly4<DIR>(o0, o1, o2, o3);
+  constexpr float h = 0.70710678118654752f;  // 1 / sqrt(2)
+  // w8^1 o1, w8^2 o2 = DIR i o2, w8^3 o3
+  const float2 t1 = (DIR < 0) ? make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x))
+                              : make_float2(h * (o1.x - o1.y), h * (o1.y + o1.x));
+  const float2 t2 = (DIR < 0) ? make_float2(o2.y, -o2.x) : make_float2(-o2.y, o2.x);
+  const float2 t3 = (DIR < 0) ? make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y))
+                              : make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+// One radix-R Stockham pass (R = 2, 4 or 8) of the CB columns in lds[M][CB], from
+// sub-transforms of size Ns to size R Ns.  tws: twiddle table exp(-2 pi i k / (2M)).
+template <int M, int CB, int DIR, int R>
+__device__ __forceinline__ void stockham_pass(float2* lds, const float2* tws, int tid, int Ns) {
+  constexpr int NB = (M / R) * CB;
+  constexpr int BPT = (NB + kThreads - 1) / kThreads;
+  const int tstep = 2 * (M / (R * Ns));  // table stride per unit of r*k
+  float2 v[BPT][R];
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int b = tid + i * kThreads;
+    if (b < NB) {
+      const int col = b % CB, j = b / CB;
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds[(j + r * (M / R)) * CB + col];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tws[r * k * tstep];
+          if (DIR > 0) w = cconj(w);
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      if constexpr (R == 8) {
+        bfly8<DIR>(v[i]);
+      } else if constexpr (R == 4) {
+        bfly4<DIR>(v[i][0], v[i][1], v[i][2], v[i][3]);
+      } else {
+        const float2 a = v[i][0];
+        v[i][0] = cadd(a, v[i][1]);
+        v[i][1] = csub(a, v[i][1]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int b = tid + i * kThreads;
+    if (b < NB) {
+      const int col = b % CB, j = b / CB;
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(base + r * Ns) * CB + col] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Complete M-point Stockham FFT (unnormalised) of the CB columns in lds[M][CB]: radix-8
+// passes, preceded by one radix-2 or radix-4 pass when log2(M) is not a multiple of 3
+// (M = 512: three passes through LDS instead of five radix-4/2 ones).
 template <int M, int CB, int DIR>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tws, int tid) {
   constexpr int LOG = log2c<M>();
   int Ns = 1;
-  if constexpr (LOG % 2 == 1) {
-    constexpr int NB = (M / 2) * CB;
-    constexpr int BPT = (NB + kThreads - 1) / kThreads;
-    float2 v0[BPT], v1[BPT];
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int b = tid + i * kThreads;
-      if (b < NB) {
-        const int col = b % CB, j = b / CB;
-        v0[i] = lds[j * CB + col];
-        v1[i] = lds[(j + M / 2) * CB + col];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int b = tid + i * kThreads;
-      if (b < NB) {
-        const int col = b % CB, j = b / CB;
-        lds[(2 * j) * CB + col] = cadd(v0[i], v1[i]);
-        lds[(2 * j + 1) * CB + col] = csub(v0[i], v1[i]);
-      }
-    }
-    __syncthreads();
+  if constexpr (LOG % 3 == 1) {
+    stockham_pass<M, CB, DIR, 2>(lds, tws, tid, Ns);
     Ns = 2;
+  } else if constexpr (LOG % 3 == 2) {
+    stockham_pass<M, CB, DIR, 4>(lds, tws, tid, Ns);
+    Ns = 4;
   }
-  constexpr int NB = (M / 4) * CB;
-  constexpr int BPT = (NB + kThreads - 1) / kThreads;
-  for (; Ns < M; Ns *= 4) {
-    const int tstep = 2 * (M / (4 * Ns));  // table stride per unit of r*k
-    float2 v[BPT][4];
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int b = tid + i * kThreads;
-      if (b < NB) {
-        const int col = b % CB, j = b / CB;
-        const int k = j & (Ns - 1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[i][r] = lds[(j + r * (M / 4)) * CB + col];
-        if (Ns > 1) {
-#pragma unroll
-          for (int r = 1; r < 4; ++r) {
-            float2 w = tws[r * k * tstep];
-            if (DIR > 0) w = cconj(w);
-            v[i][r] = cmul(v[i][r], w);
-          }
-        }
-        bfly4<DIR>(v[i][0], v[i][1], v[i][2], v[i][3]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int b = tid + i * kThreads;
-      if (b < NB) {
-        const int col = b % CB, j = b / CB;
-        const int k = j & (Ns - 1);
-        const int base = (j - k) * 4 + k;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) lds[(base + r * Ns) * CB + col] = v[i][r];
-      }
-    }
-    __syncthreads();
-  }
+  for (; Ns < M; Ns *= 8) stockham_pass<M, CB, DIR, 8>(lds, tws, tid, Ns);
+}
+
+template <int M>
+__device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __restrict__ tw, int tid) {
+  for (int k = tid; k < 2 * M; k += kThreads) tws[k] = tw[k];
 }
 
 // Workgroup number with neighbouring trace groups on the same XCD (hardware deals
@@ -125,10 +150,6 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * q8 + min(xcd, rem) + (b >> 3);
 }
 
-template <int M>
-__device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __restrict__ tw, int tid) {
-  for (int k = tid; k < 2 * M; k += kThreads) tws[k] = tw[k];
-}
 
 // ----------------------------------------------------------------- forward ---
 // VEC: Q % 4 == 0 and x 16-byte aligned (four traces per 16-byte load);
@@ -271,31 +292,48 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   const float iscale = ident_dscale != nullptr ? iscale0 * (float)*ident_dscale : iscale0;
   __syncthreads();
 
+  // Bins k and M - k of the trace pair (q, q + 1); every load of the tile is issued before
+  // any is consumed, from clamped addresses (unpredicated), invalid bins zeroed afterwards.
   auto bin2 = [&](int k, int q, float2& X0, float2& X1) {
-    X0 = X1 = make_float2(0.f, 0.f);
-    if (k >= nfmax) return;
+    const int kc = min(k, nfmax - 1);
     if (CONTIG) {  // pair of adjacent, 16-byte aligned columns (see the forward split step)
-      if (q + 1 < Q) {
-        const int r = q / nv, v = q - r * nv;
-        const float4 w = *reinterpret_cast<const float4*>(spec + ((size_t)k * n + r) * ldc + c0 + v);
-        X0 = make_float2(w.x, w.y);
-        X1 = make_float2(w.z, w.w);
-      }
+      const int qc = min(q, Q - 2);
+      const int r = qc / nv, v = qc - r * nv;
+      const float4 w = *reinterpret_cast<const float4*>(spec + ((size_t)kc * n + r) * ldc + c0 + v);
+      const bool ok = k < nfmax && q + 1 < Q;
+      X0 = ok ? make_float2(w.x, w.y) : make_float2(0.f, 0.f);
+      X1 = ok ? make_float2(w.z, w.w) : make_float2(0.f, 0.f);
     } else {
-      if (q < Q) X0 = spec[((size_t)k * n + q / nv) * ldc + c0 + q % nv];
-      if (q + 1 < Q) X1 = spec[((size_t)k * n + (q + 1) / nv) * ldc + c0 + (q + 1) % nv];
+      const int qa = min(q, Q - 1), qb = min(q + 1, Q - 1);
+      const float2 a = spec[((size_t)kc * n + qa / nv) * ldc + c0 + qa % nv];
+      const float2 b = spec[((size_t)kc * n + qb / nv) * ldc + c0 + qb % nv];
+      X0 = (k < nfmax && q < Q) ? a : make_float2(0.f, 0.f);
+      X1 = (k < nfmax && q + 1 < Q) ? b : make_float2(0.f, 0.f);
     }
-    if (conj) { X0.y = -X0.y; X1.y = -X1.y; }
-    if (k == 0 || k == M) { X0.y = 0.f; X1.y = 0.f; }  // only Re of DC and Nyquist
   };
   // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) exp(+2 pi i k / nt), two traces per task
   constexpr int CP = CB / 2;
-  for (int task = tid; task < (M / 2 + 1) * CP; task += kThreads) {
+  constexpr int NTASK = (M / 2 + 1) * CP;
+  constexpr int ITER = (NTASK + kThreads - 1) / kThreads;
+  float2 ga[ITER][2], gb[ITER][2];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int task = min(tid + it * kThreads, NTASK - 1);
     const int k = task / CP, p = task - (task / CP) * CP;
-    const int q = q0 + 2 * p;
-    float2 a[2], b[2];
-    bin2(k, q, a[0], a[1]);
-    bin2(M - k, q, b[0], b[1]);
+    bin2(k, q0 + 2 * p, ga[it][0], ga[it][1]);
+    bin2(M - k, q0 + 2 * p, gb[it][0], gb[it][1]);
+  }
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int task = tid + it * kThreads;
+    if (task >= NTASK) continue;
+    const int k = task / CP, p = task - (task / CP) * CP;
+    float2 a[2] = {ga[it][0], ga[it][1]}, b[2] = {gb[it][0], gb[it][1]};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (conj) { a[h].y = -a[h].y; b[h].y = -b[h].y; }
+      if (k == 0) { a[h].y = 0.f; b[h].y = 0.f; }  // only Re of DC (bin 0) and Nyquist (bin M)
+    }
     const float2 wk = cconj(tws[k]), wmk = cconj(tws[M - k]);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
