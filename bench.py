@@ -312,17 +312,27 @@ def bench_c3(args):
         roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": 157.3, "unit": "TFLOP/s", "frac": round(tf / 157.3, 4)}
     else:  # split bf16 products: HBM-bound on the stored kernel bytes
         gbs = kbytes / (prod_ms * 1e-3) / 1e9
-        nprod = 2 if args.prec == "bf16" else 3
+        nprod = 3 if args.prec == "bf16x2" else 2  # split products on the 16-bit matrix cores
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "mfma_bf16_TFLOPs": round(nprod * tf, 1), "mfma_bf16_frac": round(nprod * tf / 2500.0, 4)}
+                "mfma_16bit_TFLOPs": round(nprod * tf, 1), "mfma_16bit_frac": round(nprod * tf / 2500.0, 4)}
+    # transforms (HBM-bound): time samples 4 B, retained bins 8 B per trace, Q = n * nv traces
+    q_tr = n * nv
+    fft_bytes = 4.0 * spec.nt * q_tr + 8.0 * spec.nfmax * q_tr
+    fft_roof = {}
+    for i, k in ((0, "rfft"), (3, "irfft")):
+        ms = ms_stage[i] / max(1, cnt[i])
+        gb = fft_bytes / (ms * 1e-3) / 1e9
+        fft_roof[k] = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gb / HBM_PEAK_GBS, 4), "algorithmic_GB_per_launch": round(fft_bytes / 1e9, 4)}
     out = {"workload": "MDC GEMM nt=1024 nfmax=300 ns=nr=3600 nv=64, fwd+adj per step", "prec": args.prec,
            "tuning_table_ncols_fwd_adj": tune,
            "ms_per_step": round(ms_step, 3), "product_ms": round(prod_ms, 3),
            "complex_TFLOPs": round(tf, 2), "roofline": roof,
            "hbm_GBs_product": round(kbytes / (prod_ms * 1e-3) / 1e9, 1),
            "stage_ms_per_launch": {k: round(ms_stage[i] / max(1, cnt[i]), 4) for i, k in
-                                   enumerate(["rfft", "product_fwd", "product_adj", "irfft"])}}
+                                   enumerate(["rfft", "product_fwd", "product_adj", "irfft"])},
+           "fft_roofline": fft_roof}
     print(json.dumps(out), flush=True)
     op.close()
 
