@@ -193,7 +193,7 @@ mdc_status check_vec(const void* p, const char* name) {
 // pre: optional window [nr][nv] on the model side (a time-domain preconditioner P, so the
 // operator is C P, adjoint P C^H), or nullptr.
 mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st,
-                       const int* pre = nullptr, const double* in_scale = nullptr) {
+                       const int* pre = nullptr, const double* in_scale = nullptr, const Recur* rec = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
   if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
@@ -216,6 +216,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   {
     Stage t(op, 3, st);
     IfftSeg seg{out, nullptr, adjoint ? pre : nullptr, 0, 0, 1.0f};
+    attach_recur(seg, rec, 0);
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, nout, nv, nv, seg, spec_out, st)) != MDC_OK) return s;
   }
   return MDC_OK;
@@ -224,7 +225,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
 // Marchenko block operator (Eq.5): one kernel pass with columns [block for R | conj block for R*].
 mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
                            float* out1, int adjoint, hipStream_t st, int mode = 0,
-                           const double* in_scale = nullptr) {
+                           const double* in_scale = nullptr, const Recur* rec = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
   if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
@@ -260,6 +261,8 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     const float sg = mode == 1 ? 1.0f : -1.0f;
     IfftSeg a{adjoint ? out1 : out0, mode == 1 ? nullptr : (adjoint ? in1 : in0), post, 0, 0, sg, 1.0f, in_scale};
     IfftSeg b{adjoint ? out0 : out1, mode == 1 ? nullptr : (adjoint ? in0 : in1), post, 1, nv, sg, 1.0f, in_scale};
+    attach_recur(a, rec, 0);
+    attach_recur(b, rec, irfft_blocks(d.nt, n, nv));
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_out, st)) != MDC_OK) return s;
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_out, st)) != MDC_OK) return s;
   }
@@ -413,10 +416,10 @@ mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
 // device scalar, or nullptr for 1); Marchenko vectors are two contiguous blocks of `half`
 // elements.
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st, const double* in_scale) {
+                    size_t half, hipStream_t st, const double* in_scale, const Recur* rec) {
   if (kind == MDC_OP_MARCHENKO)
-    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st, 0, in_scale);
-  return apply_plain(op, in, out, nv, adjoint, st, onset, in_scale);
+    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st, 0, in_scale, rec);
+  return apply_plain(op, in, out, nv, adjoint, st, onset, in_scale, rec);
 }
 }  // namespace mdc
 

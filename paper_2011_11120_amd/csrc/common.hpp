@@ -10,11 +10,11 @@
 
 // What a captured LSQR iteration graph depends on (pointers are baked into its nodes).
 struct LsqrGraphKey {
-  int kind, nv;
+  int kind, nv, fused;
   const void *onset, *work, *x, *hist, *b;
   bool operator==(const LsqrGraphKey& o) const {
-    return kind == o.kind && nv == o.nv && onset == o.onset && work == o.work && x == o.x && hist == o.hist &&
-           b == o.b;
+    return kind == o.kind && nv == o.nv && fused == o.fused && onset == o.onset && work == o.work && x == o.x &&
+           hist == o.hist && b == o.b;
   }
 };
 
@@ -93,13 +93,41 @@ struct IfftSeg {
   float sign;          // multiplier of the transformed term
   float ident_scale = 1.0f;
   const double* ident_dscale = nullptr;  // optional device scalar multiplying ident as it is read
+  // Optional fused recurrence (LSQR / CGLS): with acc_c1 set, out = (the above) + acc_sgn *
+  // (*acc_c1) * (*acc_c2 or 1) * out_old, read and written at the same index; with part set,
+  // each workgroup writes the FP64 sum of its out^2 to part[workgroup] (irfft_blocks slots).
+  const double* acc_c1 = nullptr;
+  const double* acc_c2 = nullptr;
+  float acc_sgn = 0.f;
+  double* part = nullptr;
 };
+
+// Fused recurrence handed to an apply: out = op(in) + sgn * (*c1) * (*c2 or 1) * out (c1 may be
+// null: no update), with per-workgroup partial sums of out^2 at part (one run of slots per
+// inverse-transform segment, in segment order; irfft_blocks slots each).
+struct Recur {
+  const double* c1;
+  const double* c2;
+  float sgn;
+  double* part;
+};
+
+// Attach a fused recurrence to an inverse-transform segment; slot is its first partial-sum slot.
+inline void attach_recur(IfftSeg& seg, const Recur* rec, int slot) {
+  if (!rec) return;
+  seg.acc_c1 = rec->c1;
+  seg.acc_c2 = rec->c2;
+  seg.acc_sgn = rec->sgn;
+  seg.part = rec->part ? rec->part + slot : nullptr;
+}
 
 // FFT tables in the resident buffer: tw[k] = exp(-2 pi i k / nt), k < nt.
 mdc_status rfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int ldc, const FftSeg& seg,
                        float2* spec, hipStream_t st);
 mdc_status irfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int ldc, const IfftSeg& seg,
                         const float2* spec, hipStream_t st);
+// Workgroups of one inverse launch over n * nv traces (slots of its partial sums).
+int irfft_blocks(int nt, int n, int nv);
 
 // Kernel product over all frequencies: forward Y_f = K_f X_f (ns x nr times nr x ncols),
 // adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].  The kernel family comes from the
@@ -109,10 +137,12 @@ mdc_status product_launch(const mdc_op* op, int adjoint, const float2* in, float
 // Device state of one LSQR solve (all pointers are device memory).
 struct LsqrState {
   void* sc;                    // FP64 scalars + reduction partials (lsqr_scalars_bytes())
-  float *u, *t, *v, *w, *t2;   // data-size u, t; model-size v, w, t2
+  float *u, *t, *v, *w, *t2;   // data-size u, t; model-size v, w, t2 (t, t2 unused when fused)
   float* x;                    // solution (model size)
   double* hist;                // phibar history (niter + 1) or nullptr
   size_t model, data;          // element counts
+  double* rpart = nullptr;     // partial sums of the fused recurrences (or nullptr: separate passes)
+  int nparts_fwd = 0, nparts_adj = 0;  // slots the forward / adjoint apply fills
 };
 size_t lsqr_scalars_bytes();
 // Device scalars 1/beta and 1/alpha: u and v are kept unnormalised and every consumer scales
@@ -123,5 +153,12 @@ void lsqr_after_b(const LsqrState& s, hipStream_t st);
 void lsqr_after_init_adj(const LsqrState& s, hipStream_t st);
 void lsqr_after_fwd(const LsqrState& s, hipStream_t st);
 void lsqr_after_adj(const LsqrState& s, hipStream_t st);
+// Recurrences fused into the applies' inverse transforms; these finish the norms only.
+Recur lsqr_recur_init(const LsqrState& s);
+Recur lsqr_recur_fwd(const LsqrState& s);
+Recur lsqr_recur_adj(const LsqrState& s);
+void lsqr_after_init_adj_fused(const LsqrState& s, hipStream_t st);
+void lsqr_after_fwd_fused(const LsqrState& s, hipStream_t st);
+void lsqr_after_adj_fused(const LsqrState& s, hipStream_t st);
 
 }  // namespace mdc

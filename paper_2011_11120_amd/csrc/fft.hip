@@ -7,7 +7,10 @@
 // Stockham FFT held in LDS; a split step then yields the nt/2+1 real-signal
 // bins, of which only the first nfmax are written.  The inverse runs the same
 // steps backwards from zero-padded bins, dropping the imaginary parts of the
-// DC and Nyquist bins (what makes the pair exactly adjoint).
+// DC and Nyquist bins (what makes the pair exactly adjoint).  Its epilogue
+// applies the window Theta, the sign and the identity term of the Marchenko
+// blocks and, inside the solvers, the vector recurrence out += c * out_old
+// with one FP64 partial sum of out^2 per workgroup (the next norm).
 //
 // Layout: each workgroup owns CB consecutive traces (consecutive (n, v)
 // columns of the [nt][n][nv] array), so every global access of a time row or
@@ -280,8 +283,10 @@ template <int M, int CB, bool VEC, bool CONTIG>
 __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
     const float2* __restrict__ spec, int ldc, int c0, int conj, const float2* __restrict__ tw, int nfmax,
     int n, int nv, float scale, float* out, const float* ident,
-    const int* __restrict__ onset, float sign, float iscale0, const double* __restrict__ ident_dscale) {
+    const int* __restrict__ onset, float sign, float iscale0, const double* __restrict__ ident_dscale,
+    const double* __restrict__ acc_c1, const double* __restrict__ acc_c2, float acc_sgn, double* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
+  __shared__ double red[kThreads / 64];
   float2* lds = sh;
   float2* tws = sh + M * CB;
   constexpr int NT = 2 * M;
@@ -290,6 +295,10 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
   const int q0 = xcd_block() * CB;
   stage_twiddles<M>(tws, tw, tid);
   const float iscale = ident_dscale != nullptr ? iscale0 * (float)*ident_dscale : iscale0;
+  // fused recurrence: out += coef * out_old, coefficient formed in FP64 as the separate pass does
+  const bool acc = acc_c1 != nullptr;
+  const float coef = acc ? (float)((double)acc_sgn * *acc_c1 * (acc_c2 != nullptr ? *acc_c2 : 1.0)) : 0.f;
+  double ssq = 0.0;
   __syncthreads();
 
   // Bins k and M - k of the trace pair (q, q + 1); every load of the tile is issued before
@@ -384,25 +393,49 @@ __global__ __launch_bounds__(kThreads) void irfft_pad_kernel(
         o0 = make_float4(o0.x + iscale * d0.x, o0.y + iscale * d0.y, o0.z + iscale * d0.z, o0.w + iscale * d0.w);
         o1 = make_float4(o1.x + iscale * d1.x, o1.y + iscale * d1.y, o1.z + iscale * d1.z, o1.w + iscale * d1.w);
       }
+      if (acc) {
+        const float4 p0 = *reinterpret_cast<const float4*>(out + i0);
+        const float4 p1 = *reinterpret_cast<const float4*>(out + i1);
+        o0 = make_float4(o0.x + coef * p0.x, o0.y + coef * p0.y, o0.z + coef * p0.z, o0.w + coef * p0.w);
+        o1 = make_float4(o1.x + coef * p1.x, o1.y + coef * p1.y, o1.z + coef * p1.z, o1.w + coef * p1.w);
+      }
       *reinterpret_cast<float4*>(out + i0) = o0;
       *reinterpret_cast<float4*>(out + i1) = o1;
+      if (part != nullptr)
+        ssq += (double)o0.x * o0.x + (double)o0.y * o0.y + (double)o0.z * o0.z + (double)o0.w * o0.w +
+               (double)o1.x * o1.x + (double)o1.y * o1.y + (double)o1.z * o1.z + (double)o1.w * o1.w;
     }
   } else {
     const int col = tid % CB;
     const int q = q0 + col;
-    if (q >= Q) return;
-    const int on = (onset != nullptr) ? onset[q] : INT_MAX;
-    for (int m = tid / CB; m < M; m += kThreads / CB) {
-      const float2 z = lds[m * CB + col];
+    if (q < Q) {
+      const int on = (onset != nullptr) ? onset[q] : INT_MAX;
+      for (int m = tid / CB; m < M; m += kThreads / CB) {
+        const float2 z = lds[m * CB + col];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int t = 2 * m + h;
-        float val = (h == 0 ? z.x : z.y) * scale * sign;
-        if (!in_window(t, NT, on)) val = 0.f;
-        const size_t idx = (size_t)t * Q + q;
-        if (ident != nullptr) val += iscale * ident[idx];
-        out[idx] = val;
+        for (int h = 0; h < 2; ++h) {
+          const int t = 2 * m + h;
+          float val = (h == 0 ? z.x : z.y) * scale * sign;
+          if (!in_window(t, NT, on)) val = 0.f;
+          const size_t idx = (size_t)t * Q + q;
+          if (ident != nullptr) val += iscale * ident[idx];
+          if (acc) val += coef * out[idx];
+          out[idx] = val;
+          if (part != nullptr) ssq += (double)val * val;
+        }
       }
+    }
+  }
+  // per-workgroup partial sum of out^2 (fixed reduction order: deterministic)
+  if (part != nullptr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = ssq;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+      part[blockIdx.x] = t;
     }
   }
 }
@@ -472,7 +505,7 @@ mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const 
   }
   hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG>), dim3((Q + CB - 1) / CB), dim3(kThreads), lds, st, spec,
                      ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign, s.ident_scale,
-                     s.ident_dscale);
+                     s.ident_dscale, s.acc_c1, s.acc_c2, s.acc_sgn, s.part);
   return check_launch("irfft_pad_kernel");
 }
 
@@ -491,6 +524,12 @@ mdc_status irfft_cb(const float2* tw, int nfmax, int n, int nv, int ldc, const I
 }
 
 template <int M>
+int irfft_blocks_m(int Q) {
+  const int cb = pick_cb<M, true>(Q);
+  return (Q + cb - 1) / cb;
+}
+
+template <int M>
 mdc_status irfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const IfftSeg& s, const float2* spec,
                      hipStream_t st) {
   constexpr int WIDE = wide_cb<M, true>();
@@ -499,6 +538,21 @@ mdc_status irfft_one(const float2* tw, int nfmax, int n, int nv, int ldc, const 
 }
 
 }  // namespace
+
+int irfft_blocks(int nt, int n, int nv) {
+  const int Q = n * nv;
+  switch (nt) {
+    case 16: return irfft_blocks_m<8>(Q);
+    case 32: return irfft_blocks_m<16>(Q);
+    case 64: return irfft_blocks_m<32>(Q);
+    case 128: return irfft_blocks_m<64>(Q);
+    case 256: return irfft_blocks_m<128>(Q);
+    case 512: return irfft_blocks_m<256>(Q);
+    case 1024: return irfft_blocks_m<512>(Q);
+    case 2048: return irfft_blocks_m<1024>(Q);
+    default: return 0;
+  }
+}
 
 mdc_status rfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int ldc, const FftSeg& seg,
                        float2* spec, hipStream_t st) {

@@ -16,7 +16,7 @@
 namespace mdc {
 
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st, const double* in_scale = nullptr);
+                    size_t half, hipStream_t st, const double* in_scale = nullptr, const Recur* rec = nullptr);
 
 namespace {
 
@@ -72,10 +72,11 @@ __global__ __launch_bounds__(kThreads) void sumsq(const float* __restrict__ x, s
 }
 
 // norm = sqrt(sum of partials) into *dst; *inv = 1/norm (1 if norm == 0)
-__global__ __launch_bounds__(kThreads) void finish_norm(Scalars* sc, double* dst, double* inv, int nparts) {
+__global__ __launch_bounds__(kThreads) void finish_norm(const double* __restrict__ part, double* dst, double* inv,
+                                                        int nparts) {
   __shared__ double sh[kThreads / 64];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += sc->part[i];
+  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += part[i];
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(t);
@@ -190,7 +191,7 @@ void lsqr_after_b(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
   const int gd = grid_for(s.data);
   hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, s.u, s.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, &sc->uinv, gd);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->beta, &sc->uinv, gd);
 }
 
 // alpha v = t2 (= A^H u), w = v, x = 0
@@ -199,7 +200,7 @@ void lsqr_after_init_adj(const LsqrState& s, hipStream_t st) {
   const int gm = grid_for(s.model);
   hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.t2, (const double*)nullptr,
                      (const double*)nullptr, 0.0, s.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, &sc->vinv, gm);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->alpha, &sc->vinv, gm);
   hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc, s.hist);
 }
 
@@ -209,7 +210,7 @@ void lsqr_after_fwd(const LsqrState& s, hipStream_t st) {
   const int gd = grid_for(s.data);
   hipLaunchKernelGGL(lin_norm, dim3(gd), dim3(kThreads), 0, st, s.u, s.t, s.u, (const double*)&sc->alpha,
                      (const double*)&sc->uinv, -1.0, s.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->beta, &sc->uinv, gd);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->beta, &sc->uinv, gd);
 }
 
 // alpha v = t2 - beta v  (t2 = A^H u); rotation; x += phi/rho w; w = v - theta/rho w
@@ -218,7 +219,38 @@ void lsqr_after_adj(const LsqrState& s, hipStream_t st) {
   const int gm = grid_for(s.model);
   hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, s.v, s.t2, s.v, (const double*)&sc->beta,
                      (const double*)&sc->vinv, -1.0, s.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->alpha, &sc->vinv, gm);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->alpha, &sc->vinv, gm);
+  hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
+  hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
+}
+
+// The same recurrences fused into the applies: the forward apply's inverse transform forms
+// beta u = A v - alpha u in place and the adjoint's alpha v = A^H u - beta v, each workgroup
+// leaving the FP64 sum of its squares in rpart; these finish the norms (and the rotation).
+Recur lsqr_recur_fwd(const LsqrState& s) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  return Recur{&sc->alpha, &sc->uinv, -1.0f, s.rpart};
+}
+Recur lsqr_recur_adj(const LsqrState& s) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  return Recur{&sc->beta, &sc->vinv, -1.0f, s.rpart};
+}
+Recur lsqr_recur_init(const LsqrState& s) { return Recur{nullptr, nullptr, 0.f, s.rpart}; }
+// alpha v = A^H u written by the adjoint itself; w = v, x = 0
+void lsqr_after_init_adj_fused(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gm = grid_for(s.model);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, s.rpart, &sc->alpha, &sc->vinv, s.nparts_adj);
+  hipLaunchKernelGGL(init_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc, s.hist);
+}
+void lsqr_after_fwd_fused(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, s.rpart, &sc->beta, &sc->uinv, s.nparts_fwd);
+}
+void lsqr_after_adj_fused(const LsqrState& s, hipStream_t st) {
+  Scalars* sc = static_cast<Scalars*>(s.sc);
+  const int gm = grid_for(s.model);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, s.rpart, &sc->alpha, &sc->vinv, s.nparts_adj);
   hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
   hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
 }
@@ -227,23 +259,32 @@ namespace {
 
 struct Sizes {
   size_t model, data;  // element counts
+  int parts_fwd, parts_adj;  // partial-sum slots of the fused recurrences
 };
 
 Sizes sizes_of(const mdc_desc& d, const lsqr_desc& ld) {
   Sizes z{};
   if (ld.kind == MDC_OP_MARCHENKO) {
     z.model = z.data = 2ull * d.nt * d.ns * ld.nv;
+    z.parts_fwd = z.parts_adj = 2 * irfft_blocks(d.nt, d.ns, ld.nv);
   } else {
     z.model = (size_t)d.nt * d.nr * ld.nv;
     z.data = (size_t)d.nt * d.ns * ld.nv;
+    z.parts_fwd = irfft_blocks(d.nt, d.ns, ld.nv);
+    z.parts_adj = irfft_blocks(d.nt, d.nr, ld.nv);
   }
   return z;
+}
+
+size_t parts_bytes_of(const Sizes& z) {
+  return align_up((size_t)(z.parts_fwd > z.parts_adj ? z.parts_fwd : z.parts_adj) * sizeof(double), 256);
 }
 
 size_t work_bytes_of(const Sizes& z) {
   size_t b = lsqr_scalars_bytes();
   b += 2 * align_up(z.data * 4, 256);   // u, t
   b += 3 * align_up(z.model * 4, 256);  // v, w, t2
+  b += parts_bytes_of(z);               // partial sums of the fused recurrences
   return b;
 }
 
@@ -285,7 +326,13 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   S.t = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
   S.v = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
   S.w = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
-  S.t2 = reinterpret_cast<float*>(p);
+  S.t2 = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  const char* f = getenv("MDC_LSQR_FUSE");
+  if (!(f && f[0] == '0')) {
+    S.rpart = reinterpret_cast<double*>(p);
+    S.nparts_fwd = z.parts_fwd;
+    S.nparts_adj = z.parts_adj;
+  }
   S.x = x;
   S.hist = hist;
   S.model = z.model;
@@ -296,11 +343,26 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
 
   hipLaunchKernelGGL(copy_f32, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.u, b, z.data);
   lsqr_after_b(S, st);
-  if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st, lsqr_uinv(S))) != MDC_OK) return s;
-  lsqr_after_init_adj(S, st);
+  if (S.rpart) {
+    const Recur ri = lsqr_recur_init(S);
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, st, lsqr_uinv(S), &ri)) != MDC_OK) return s;
+    lsqr_after_init_adj_fused(S, st);
+  } else {
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st, lsqr_uinv(S))) != MDC_OK) return s;
+    lsqr_after_init_adj(S, st);
+  }
   if ((s = check_launch("lsqr init")) != MDC_OK) return s;
   auto iteration = [&](hipStream_t q) -> mdc_status {
     mdc_status e;
+    if (S.rpart) {
+      const Recur rf = lsqr_recur_fwd(S);
+      if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.u, half, q, lsqr_vinv(S), &rf)) != MDC_OK) return e;
+      lsqr_after_fwd_fused(S, q);
+      const Recur ra = lsqr_recur_adj(S);
+      if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, q, lsqr_uinv(S), &ra)) != MDC_OK) return e;
+      lsqr_after_adj_fused(S, q);
+      return check_launch("lsqr iteration");
+    }
     if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q, lsqr_vinv(S))) != MDC_OK) return e;
     lsqr_after_fwd(S, q);
     if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q, lsqr_uinv(S))) != MDC_OK) return e;
@@ -318,7 +380,7 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   }
   // Capture one iteration (identical launches every time: the iteration counter lives on the
   // device) on the op's private stream, then replay it on the caller's stream.
-  const LsqrGraphKey key{kind, ld.nv, ld.onset, work, x, hist, b};
+  const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, ld.onset, work, x, hist, b};
   if (!op->lsqr_exec || !(op->lsqr_key == key)) {
     if (op->lsqr_exec) {
       hipGraphExecDestroy(op->lsqr_exec);
@@ -360,32 +422,45 @@ mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   float* r = reinterpret_cast<float*>(w); w += align_up(z.data * 4, 256);
   float* q = reinterpret_cast<float*>(w); w += align_up(z.data * 4, 256);
   float* sv = reinterpret_cast<float*>(w); w += align_up(z.model * 4, 256);
-  float* p = reinterpret_cast<float*>(w);
+  float* p = reinterpret_cast<float*>(w); w += align_up(z.model * 4, 256);
+  // ||q|| and ||s|| from partial sums the inverse transforms leave (no separate pass)
+  const char* f = getenv("MDC_LSQR_FUSE");
+  double* rpart = (f && f[0] == '0') ? nullptr : reinterpret_cast<double*>(w);
+  const Recur rnorm{nullptr, nullptr, 0.f, rpart};
+  const Recur* rn = rpart ? &rnorm : nullptr;
   const size_t half = z.model / 2;
   const int gd = grid_for(z.data), gm = grid_for(z.model), gx = grid_for(z.model > z.data ? z.model : z.data);
   mdc_status s;
   // r = b ; s = A^H r ; p = s ; x = 0
   hipLaunchKernelGGL(copy_f32, dim3(gd), dim3(kThreads), 0, st, r, b, z.data);
   hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, &sc->inv, gd);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->rn, &sc->inv, gd);
   if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
   hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, sv, (const double*)nullptr, (const double*)nullptr, 0.0, z.model, sc);
-  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, &sc->inv, gm);
+  hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->sn, &sc->inv, gm);
   hipLaunchKernelGGL(zero_vec, dim3(gm), dim3(kThreads), 0, st, x, z.model);
   hipLaunchKernelGGL(cg_init, dim3(1), dim3(64), 0, st, sc, hist);
   for (int it = 1; it <= ld.niter; ++it) {
     // q = A p ; alpha = gamma / ||q||^2 ; x += alpha p ; r -= alpha q
-    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 0, p, q, half, st)) != MDC_OK) return s;
-    hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, q, z.data, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->qn, &sc->inv, gd);
+    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 0, p, q, half, st, nullptr, rn)) != MDC_OK) return s;
+    if (rpart) {
+      hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, rpart, &sc->qn, &sc->inv, z.parts_fwd);
+    } else {
+      hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, q, z.data, sc);
+      hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->qn, &sc->inv, gd);
+    }
     hipLaunchKernelGGL(cg_alpha, dim3(1), dim3(64), 0, st, sc);
     hipLaunchKernelGGL(cg_xr, dim3(gx), dim3(kThreads), 0, st, x, p, r, q, z.model, z.data, sc);
     hipLaunchKernelGGL(sumsq, dim3(gd), dim3(kThreads), 0, st, r, z.data, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->rn, &sc->inv, gd);
+    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->rn, &sc->inv, gd);
     // s = A^H r ; beta = ||s||^2 / gamma ; p = s + beta p
-    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st)) != MDC_OK) return s;
-    hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, sv, z.model, sc);
-    hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc, &sc->sn, &sc->inv, gm);
+    if ((s = apply_op(op, ld.kind, ld.onset, ld.nv, 1, r, sv, half, st, nullptr, rn)) != MDC_OK) return s;
+    if (rpart) {
+      hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, rpart, &sc->sn, &sc->inv, z.parts_adj);
+    } else {
+      hipLaunchKernelGGL(sumsq, dim3(gm), dim3(kThreads), 0, st, sv, z.model, sc);
+      hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->sn, &sc->inv, gm);
+    }
     hipLaunchKernelGGL(cg_beta, dim3(1), dim3(64), 0, st, sc, hist);
     hipLaunchKernelGGL(lin_norm, dim3(gm), dim3(kThreads), 0, st, p, sv, p, (const double*)&sc->beta, (const double*)nullptr, 1.0, z.model, sc);
     if ((s = check_launch("cgls iteration")) != MDC_OK) return s;

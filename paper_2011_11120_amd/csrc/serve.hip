@@ -113,11 +113,15 @@ struct Request {
   std::chrono::steady_clock::time_point arrival, finish;
 };
 
+// Partial-sum slots of one request's fused recurrences (two inverse segments per apply).
+int parts_for(const mdc_desc& d, int nv) { return 2 * irfft_blocks(d.nt, d.ns, nv); }
+
 size_t slot_bytes_for(const mdc_desc& d, int nv) {
   const size_t vec = 2ull * d.nt * d.ns * nv * 4;  // two Marchenko blocks
   size_t b = 2 * align_up((size_t)d.ns * nv * 4, 256);  // onset, keep
   b += lsqr_scalars_bytes();
-  b += 5 * align_up(vec, 256);                        // u, t, v, w, t2
+  b += align_up((size_t)parts_for(d, nv) * sizeof(double), 256);  // partial sums
+  b += 3 * align_up(vec, 256);                        // u, v, w (recurrences fused into the applies)
   return b;
 }
 
@@ -244,20 +248,26 @@ mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hi
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, st, r->S.u + half, half);
       lsqr_after_b(r->S, st);
-    } else if (fwd) {  // t0 = v0 - d Theta R v1 ; t1 = v1 - d Theta R* v0
-      IfftSeg a{r->S.t, r->S.v, r->onset, 0, r->c0, -dsc, 1.0f, lsqr_vinv(r->S)};
-      IfftSeg b{r->S.t + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_vinv(r->S)};
+    } else if (fwd) {  // beta u = A v - alpha u: [v0 - d Theta R v1 ; v1 - d Theta R* v0] - alpha u, in place
+      const Recur rec = lsqr_recur_fwd(r->S);
+      IfftSeg a{r->S.u, r->S.v, r->onset, 0, r->c0, -dsc, 1.0f, lsqr_vinv(r->S)};
+      IfftSeg b{r->S.u + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_vinv(r->S)};
+      attach_recur(a, &rec, 0);
+      attach_recur(b, &rec, r->S.nparts_fwd / 2);
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
-      lsqr_after_fwd(r->S, st);
-    } else {  // t2_1 = u1 - d keep R^H Theta u0 ; t2_0 = u0 - d keep R*^H Theta u1
+      lsqr_after_fwd_fused(r->S, st);
+    } else {  // alpha v = A^H u - beta v: [u0 - d keep R*^H Theta u1 ; u1 - d keep R^H Theta u0] - beta v
       const int* km = r->decim > 1 ? r->keep : nullptr;
-      IfftSeg a{r->S.t2 + half, r->S.u + half, km, 0, r->c0, -dsc, 1.0f, lsqr_uinv(r->S)};
-      IfftSeg b{r->S.t2, r->S.u, km, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_uinv(r->S)};
+      const Recur rec = r->phase == kInitAdj ? lsqr_recur_init(r->S) : lsqr_recur_adj(r->S);
+      IfftSeg a{r->S.v + half, r->S.u + half, km, 0, r->c0, -dsc, 1.0f, lsqr_uinv(r->S)};
+      IfftSeg b{r->S.v, r->S.u, km, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_uinv(r->S)};
+      attach_recur(a, &rec, 0);
+      attach_recur(b, &rec, r->S.nparts_adj / 2);
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
-      if (r->phase == kInitAdj) lsqr_after_init_adj(r->S, st);
-      else lsqr_after_adj(r->S, st);
+      if (r->phase == kInitAdj) lsqr_after_init_adj_fused(r->S, st);
+      else lsqr_after_adj_fused(r->S, st);
     }
   }
   return check_launch("serve step");
@@ -344,11 +354,12 @@ bool admit(mdc_server* S, Request* r) {
   r->onset = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
   r->keep = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
   r->S.sc = p; p += lsqr_scalars_bytes();
+  r->S.rpart = reinterpret_cast<double*>(p); p += align_up((size_t)parts_for(d, r->nv) * sizeof(double), 256);
+  r->S.nparts_fwd = r->S.nparts_adj = parts_for(d, r->nv);
   r->S.u = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
-  r->S.t = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
   r->S.v = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
-  r->S.w = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
-  r->S.t2 = reinterpret_cast<float*>(p);
+  r->S.w = reinterpret_cast<float*>(p);
+  r->S.t = r->S.t2 = nullptr;
   r->S.x = r->x_out;
   r->S.hist = r->hist;
   r->S.model = r->S.data = vec;

@@ -133,3 +133,56 @@ def test_lsqr_graph_replays_match_eager(mdcmod, monkeypatch):
         assert torch.equal(xg, xe) and torch.equal(hg, he), f"replay {rep}"
         op.forward(other)  # eager work between replays
         torch.cuda.synchronize()
+
+
+# (kind, nt, nfmax, ns, nr, nv): rectangular MDC with an odd trace count (scalar epilogue), with a
+# vector epilogue, with wide tiles and more than a thousand partial-sum slots; Marchenko blocks.
+FUSED_CASES = [
+    ("mdc", 64, 20, 35, 29, 1),
+    ("mdc", 64, 20, 36, 40, 3),
+    ("mdc", 64, 20, 1030, 1030, 8),
+    ("marchenko", 64, 25, 25, 25, 2),
+    ("marchenko", 128, 40, 49, 49, 3),
+]
+
+
+@pytest.mark.parametrize("solver", ["lsqr", "cgls"])
+@pytest.mark.parametrize("case", FUSED_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_fused_norms_match_separate_passes_and_oracle(mdcmod, monkeypatch, case, solver):
+    """The recurrences and norms fused into the inverse transforms equal the separate vector passes
+    (same per-element arithmetic, partial sums grouped differently) and the FP64 oracle."""
+    kind, nt, nfmax, ns, nr, nv = case
+    print(f"fused {solver} {case}", flush=True)
+    niter = 6
+    if kind == "mdc":
+        K = synth.random_complex_kernel(nfmax, ns, nr, seed=11)
+        K *= 0.8 / max(power.spectral_norm(K[f], iters=40) for f in range(nfmax))
+        op = op_for(mdcmod, K, nt, nv)
+        b = synth.gaussian((nt, ns, nv), seed=12)
+        args = dict(nv=nv)
+        A = lambda v: [om.mdc_forward(K, v[0])]
+        AH = lambda u: [om.mdc_adjoint(K, u[0])]
+        bl = [b]
+    else:
+        K, onset = marchenko_case(nt, nfmax, int(round(ns ** 0.5)), nv, seed=13)
+        op = op_for(mdcmod, K, nt, 2 * nv)
+        fd = synth.ricker_spikes(nt, ns, nv)
+        d0, d1 = omc.data(K, onset, fd)
+        b = np.stack([d0, d1])
+        args = dict(kind=mdcmod.MDC_OP_MARCHENKO, nv=nv, onset=dev(onset, torch.int32))
+        A = lambda v: list(omc.forward(K, onset, *v))
+        AH = lambda u: list(omc.adjoint(K, onset, *u))
+        bl = [d0, d1]
+    run = op.lsqr if solver == "lsqr" else op.cgls
+    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
+    xf, hf = run(dev(b), niter, **args)
+    xf, hf = host(xf), host(hf)
+    monkeypatch.setenv("MDC_LSQR_FUSE", "0")
+    xs, hs = run(dev(b), niter, **args)
+    xs, hs = host(xs), host(hs)
+    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
+    assert rel2(xf, xs) < 1e-6
+    assert np.max(np.abs(hf - hs)) / hs[0] < 1e-6
+    xr, hr = (ol.lsqr if solver == "lsqr" else ol.cgls)(A, AH, bl, niter)
+    assert rel2(xf, np.stack(xr) if kind == "marchenko" else xr[0]) < TOL
+    assert np.max(np.abs(hf - hr) / hr[0]) < TOL
