@@ -79,6 +79,9 @@ SHAPES = [
     (128, 30, 90, 258, 5),
     (128, 40, 1030, 1030, 9),   # wide FFT blocks, n*nv not a multiple of 4 (scalar FFT path)
     (64, 20, 2050, 2050, 4),    # wide FFT blocks, vector path, ragged last block
+    (512, 100, 64, 72, 132),    # wide FFT tiles at nt = 512 (n * nv >= 8192), GEMM with a ragged column tile
+    (1024, 200, 64, 64, 130),   # wide FFT tiles at nt = 1024
+    (2048, 300, 40, 33, 260),   # wide FFT tiles at nt = 2048
 ]
 
 
