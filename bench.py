@@ -160,7 +160,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the MDC path here is single-GPU "
-              "(frequency sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+              "(frequency sharding across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
