@@ -233,7 +233,12 @@ mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_
 
 /* b: data (device, float); x: model output (device, float, overwritten);
  * hist: device double array of niter+1 entries receiving phibar (the residual
- * norm estimate) after each iteration, or NULL; work: device workspace. */
+ * norm estimate) after each iteration, or NULL; work: device workspace.
+ * The three-term recurrences and their norms run inside the operator's inverse
+ * transform (environment MDC_LSQR_FUSE=0 runs them as separate vector passes:
+ * the same per-element arithmetic, norms summed in a different grouping), and
+ * iterations after the first replay a captured graph (MDC_LSQR_GRAPH=0 runs
+ * them eagerly). */
 mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist,
                       void* work, size_t work_bytes, void* stream);
 
