@@ -133,6 +133,30 @@ __global__ __launch_bounds__(kThreads) void update_xw(float* __restrict__ x, flo
     w[i] = v[i] * vi + cw * wi;
   }
 }
+// the same four elements at a time (n4 = n / 4, every vector 16-byte aligned)
+__global__ __launch_bounds__(kThreads) void update_xw4(float4* __restrict__ x, float4* __restrict__ w,
+                                                       const float4* __restrict__ v, size_t n4, const Scalars* sc) {
+  const float cx = (float)sc->cx, cw = (float)sc->cw, vi = (float)sc->vinv;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n4; i += (size_t)gridDim.x * kThreads) {
+    const float4 wi = w[i], vv = v[i], xi = x[i];
+    x[i] = make_float4(xi.x + cx * wi.x, xi.y + cx * wi.y, xi.z + cx * wi.z, xi.w + cx * wi.w);
+    w[i] = make_float4(vv.x * vi + cw * wi.x, vv.y * vi + cw * wi.y, vv.z * vi + cw * wi.z, vv.w * vi + cw * wi.w);
+  }
+}
+
+void launch_update_xw(float* x, float* w, const float* v, size_t n, const Scalars* sc, hipStream_t st) {
+  if (n % 4 == 0 && aligned(x, 16) && aligned(w, 16) && aligned(v, 16)) {
+    const size_t n4 = n / 4;
+    const size_t b = (n4 + kThreads - 1) / kThreads;
+    const int gd = (int)(b < 2048 ? (b == 0 ? 1 : b) : 2048);
+    hipLaunchKernelGGL(update_xw4, dim3(gd), dim3(kThreads), 0, st, reinterpret_cast<float4*>(x),
+                       reinterpret_cast<float4*>(w), reinterpret_cast<const float4*>(v), n4, sc);
+  } else {
+    const size_t b = (n + kThreads - 1) / kThreads;
+    const int gd = (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
+    hipLaunchKernelGGL(update_xw, dim3(gd), dim3(kThreads), 0, st, x, w, v, n, sc);
+  }
+}
 
 // ---------------------------------------------------------------- CGLS ----
 // gamma = ||s||^2 (start), hist[0] = ||r||
@@ -221,7 +245,7 @@ void lsqr_after_adj(const LsqrState& s, hipStream_t st) {
                      (const double*)&sc->vinv, -1.0, s.model, sc);
   hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, sc->part, &sc->alpha, &sc->vinv, gm);
   hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
-  hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
+  launch_update_xw(s.x, s.w, s.v, s.model, sc, st);
 }
 
 // The same recurrences fused into the applies: the forward apply's inverse transform forms
@@ -249,10 +273,9 @@ void lsqr_after_fwd_fused(const LsqrState& s, hipStream_t st) {
 }
 void lsqr_after_adj_fused(const LsqrState& s, hipStream_t st) {
   Scalars* sc = static_cast<Scalars*>(s.sc);
-  const int gm = grid_for(s.model);
   hipLaunchKernelGGL(finish_norm, dim3(1), dim3(kThreads), 0, st, s.rpart, &sc->alpha, &sc->vinv, s.nparts_adj);
   hipLaunchKernelGGL(givens, dim3(1), dim3(64), 0, st, sc, s.hist);
-  hipLaunchKernelGGL(update_xw, dim3(gm), dim3(kThreads), 0, st, s.x, s.w, s.v, s.model, sc);
+  launch_update_xw(s.x, s.w, s.v, s.model, sc, st);
 }
 
 namespace {
