@@ -27,7 +27,7 @@
 namespace mdc {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // threads per workgroup of the narrow tiles and short transforms
 
 template <int M>
 constexpr int log2c() {
