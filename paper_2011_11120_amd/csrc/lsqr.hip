@@ -133,29 +133,10 @@ __global__ __launch_bounds__(kThreads) void update_xw(float* __restrict__ x, flo
     w[i] = v[i] * vi + cw * wi;
   }
 }
-// the same four elements at a time (n4 = n / 4, every vector 16-byte aligned)
-__global__ __launch_bounds__(kThreads) void update_xw4(float4* __restrict__ x, float4* __restrict__ w,
-                                                       const float4* __restrict__ v, size_t n4, const Scalars* sc) {
-  const float cx = (float)sc->cx, cw = (float)sc->cw, vi = (float)sc->vinv;
-  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n4; i += (size_t)gridDim.x * kThreads) {
-    const float4 wi = w[i], vv = v[i], xi = x[i];
-    x[i] = make_float4(xi.x + cx * wi.x, xi.y + cx * wi.y, xi.z + cx * wi.z, xi.w + cx * wi.w);
-    w[i] = make_float4(vv.x * vi + cw * wi.x, vv.y * vi + cw * wi.y, vv.z * vi + cw * wi.z, vv.w * vi + cw * wi.w);
-  }
-}
-
 void launch_update_xw(float* x, float* w, const float* v, size_t n, const Scalars* sc, hipStream_t st) {
-  if (n % 4 == 0 && aligned(x, 16) && aligned(w, 16) && aligned(v, 16)) {
-    const size_t n4 = n / 4;
-    const size_t b = (n4 + kThreads - 1) / kThreads;
-    const int gd = (int)(b < 2048 ? (b == 0 ? 1 : b) : 2048);
-    hipLaunchKernelGGL(update_xw4, dim3(gd), dim3(kThreads), 0, st, reinterpret_cast<float4*>(x),
-                       reinterpret_cast<float4*>(w), reinterpret_cast<const float4*>(v), n4, sc);
-  } else {
-    const size_t b = (n + kThreads - 1) / kThreads;
-    const int gd = (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
-    hipLaunchKernelGGL(update_xw, dim3(gd), dim3(kThreads), 0, st, x, w, v, n, sc);
-  }
+  const size_t b = (n + kThreads - 1) / kThreads;
+  const int gd = (int)(b < (size_t)kParts ? (b == 0 ? 1 : b) : kParts);
+  hipLaunchKernelGGL(update_xw, dim3(gd), dim3(kThreads), 0, st, x, w, v, n, sc);
 }
 
 // ---------------------------------------------------------------- CGLS ----
