@@ -16,7 +16,7 @@
  * applied besides the conjugate transpose of each slice.
  *
  * Memory: the library never allocates device memory.  The caller obtains
- * sizes from mdc_query_sizes / lsqr_query_sizes / serve_query_sizes and
+ * sizes from mdc_query_sizes / lsqr_query_sizes / serve_request_bytes and
  * passes device buffers it owns (e.g. from PyTorch); the library never frees
  * them.  Host-side handles (mdc_op, mdc_server) are owned by the library
  * and released by the matching *_destroy call.
@@ -85,8 +85,9 @@ const char* mdc_last_error(void);
 
 /* Bytes of the resident buffer (kernel + tables, 256-byte aligned pieces) and
  * of the per-apply workspace (spectra of max_cols columns; for the 16-bit
- * formats also one spectrum split into bf16 hi and lo parts, padded to
- * multiples of 64 columns and 32 traces, for the matrix-core product). */
+ * formats also one spectrum split into 16-bit hi and lo parts, padded to
+ * multiples of 64 columns and 96 traces, and nfmax per-frequency maxima, for
+ * the matrix-core product). */
 mdc_status mdc_query_sizes(const mdc_desc* desc, size_t* resident_bytes, size_t* workspace_bytes);
 
 /* Create an operator over caller-owned device buffers `resident` and `workspace`
