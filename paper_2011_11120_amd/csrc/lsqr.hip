@@ -7,7 +7,10 @@
 // c, s, theta, phi, phibar) and every norm is FP64 and lives on the device,
 // so the host enqueues the whole solve without synchronising.  Norms are
 // reduced in two fixed-shape stages (per-block FP64 partials, then one block),
-// so results do not depend on scheduling.
+// so results do not depend on scheduling.  By default the three-term
+// recurrences and their partial norms run inside the operator's inverse
+// transform (one partial per transform workgroup), leaving one x/w update
+// pass per iteration.
 #include <cmath>
 #include <cstdlib>
 
