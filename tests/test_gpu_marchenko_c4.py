@@ -126,3 +126,24 @@ def test_c4_lsqr_residual_identity(mdcmod, c4):
     assert np.all(np.diff(h) <= 1e-6 * h[0])               # phibar never increases
     assert h[-1] < 1e-2 * h[0]                              # 30 iterations converge on M with ||K_f|| <= 0.5
     assert abs(float(res) - h[-1]) < 1e-4 * h[0]            # ||d - M x|| == phibar (exact arithmetic identity)
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s"])
+def test_c4_low_precision_solution_matches_fp32(mdcmod, c4, prec):
+    """Full size, 30 iterations: the solution with a 16-bit stored kernel stays within the 1e-3
+    relative model error of the FP32 solution (same right-hand side, same onsets)."""
+    case, op = c4
+    on = dev(case.onset, torch.int32)
+    dg = op.marchenko_data(on, dev(case.fd))
+    x32, _ = op.lsqr(dg, 30, kind=mdcmod.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+    x32 = x32.cpu().numpy().astype(np.float64)
+    print(f"c4 {prec}: generating kernel on device", flush=True)
+    lp = mdcmod.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv, prec=prec)
+    lp.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
+    xl, hist = lp.lsqr(dg, 30, kind=mdcmod.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+    err = rel2(xl.cpu().numpy().astype(np.float64), x32)
+    print(f"c4 {prec}: relative model difference to FP32 {err:.2e}", flush=True)
+    assert err < 1e-3
+    h = hist.cpu().numpy()
+    assert h[-1] < 1e-2 * h[0]
+    lp.close()
