@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--skip", type=int, default=2, help="c5: first completions left out of the latency stats")
     ap.add_argument("--c5-precs", default="fp32,fp16s", help="c5: kernel formats to serve, in order")
     ap.add_argument("--c5-max-cols", type=int, default=384, help="c5: column budget (2 per focusing point)")
-    ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2"], default="fp32",
+    ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2", "fp16"], default="fp32",
                     help="kernel storage format for the c3/c4 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -320,12 +320,12 @@ def bench_c3(args):
     flops = 8.0 * spec.nfmax * n * n * nv
     prod_ms = (ms_stage[1] + ms_stage[2]) / max(1, cnt[1] + cnt[2])
     tf = flops / (prod_ms * 1e-3) / 1e12
-    kbytes = {"fp32": 8, "bf16x2": 8, "fp16s": 4, "bf16": 4}[args.prec] * spec.nfmax * n * n
+    kbytes = {"fp32": 8, "bf16x2": 8, "fp16s": 4, "bf16": 4, "fp16": 4}[args.prec] * spec.nfmax * n * n
     if args.prec == "fp32":
         roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": 157.3, "unit": "TFLOP/s", "frac": round(tf / 157.3, 4)}
     else:  # split bf16 products: HBM-bound on the stored kernel bytes
         gbs = kbytes / (prod_ms * 1e-3) / 1e9
-        nprod = 3 if args.prec == "bf16x2" else 2  # split products on the 16-bit matrix cores
+        nprod = {"bf16x2": 3, "fp16": 1}.get(args.prec, 2)  # products on the 16-bit matrix cores
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "mfma_16bit_TFLOPs": round(nprod * tf, 1), "mfma_16bit_frac": round(nprod * tf / 2500.0, 4)}

@@ -66,8 +66,12 @@ typedef enum {
  *   MDC_FP32   complex64, 8 bytes per element.
  *   MDC_FP16S  FP16 pairs scaled by a power of two per frequency slice (4 bytes).
  *   MDC_BF16   BF16 pairs (4 bytes).
- *   MDC_BF16X2 BF16 hi + lo pairs, hi = RNE(k), lo = RNE(k - hi) (8 bytes).  */
-typedef enum { MDC_FP32 = 0, MDC_FP16S = 1, MDC_BF16 = 2, MDC_BF16X2 = 3 } mdc_prec;
+ *   MDC_BF16X2 BF16 hi + lo pairs, hi = RNE(k), lo = RNE(k - hi) (8 bytes).
+ *   MDC_FP16   the MDC_FP16S kernel; on the matrix cores the spectra are rounded
+ *              once to FP16 (power-of-two scale per frequency) instead of split
+ *              into hi + lo, so the product takes one pass instead of two (about
+ *              2^-11 relative error per apply instead of 2^-12).  */
+typedef enum { MDC_FP32 = 0, MDC_FP16S = 1, MDC_BF16 = 2, MDC_BF16X2 = 3, MDC_FP16 = 4 } mdc_prec;
 
 typedef struct mdc_op mdc_op;
 

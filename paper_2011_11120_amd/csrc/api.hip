@@ -44,6 +44,7 @@ size_t store_bytes(const mdc_desc& d) {
   switch (d.prec) {
     case MDC_FP32: return elems * 8;
     case MDC_FP16S: return elems * 4;
+    case MDC_FP16: return elems * 4;
     case MDC_BF16: return elems * 4;
     case MDC_BF16X2: return elems * 8;
   }
@@ -125,7 +126,7 @@ mdc_status check_desc(const mdc_desc* d) {
   if (d->nfmax < 1 || d->nfmax > d->nt / 2 + 1) return fail(MDC_EINVAL, "nfmax=%d outside [1, nt/2+1]", d->nfmax);
   if (d->ns < 1 || d->nr < 1) return fail(MDC_EINVAL, "ns=%d, nr=%d must be positive", d->ns, d->nr);
   if (d->max_cols < 1 || d->max_cols > 4096) return fail(MDC_EINVAL, "max_cols=%d outside [1, 4096]", d->max_cols);
-  if (d->prec < MDC_FP32 || d->prec > MDC_BF16X2) return fail(MDC_EINVAL, "unknown storage format %d", (int)d->prec);
+  if (d->prec < MDC_FP32 || d->prec > MDC_FP16) return fail(MDC_EINVAL, "unknown storage format %d", (int)d->prec);
   return MDC_OK;
 }
 
@@ -484,6 +485,7 @@ mdc_status mdc_set_kernel(mdc_op* op, const void* K, double scale, const float* 
     case MDC_BF16: s = launch_load<StoreBF16>(op, k, scale, col_weight, st); break;
     case MDC_BF16X2: s = launch_load<StoreBF16X2>(op, k, scale, col_weight, st); break;
     case MDC_FP16S:
+    case MDC_FP16:
       if (hipMemsetAsync(op->fscale, 0, (size_t)op->d.nfmax * 4, st) != hipSuccess)
         return fail(MDC_EDEVICE, "clearing the scale table failed");
       if ((s = launch_load<StoreMax>(op, k, scale, col_weight, st)) != MDC_OK) return s;
@@ -561,6 +563,7 @@ mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, flo
       ok = hipMemcpyAsync(&v, base + (row * ldk + r) * 8, 8, hipMemcpyDeviceToHost, st) == hipSuccess;
       break;
     case MDC_FP16S:
+    case MDC_FP16:
       ok = hipMemcpyAsync(&w[0], base + (row * ldk + r) * 4, 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
            hipMemcpyAsync(&sf, op->fscale + f, 4, hipMemcpyDeviceToHost, st) == hipSuccess;
       break;
@@ -589,7 +592,8 @@ mdc_status mdc_kernel_element(mdc_op* op, int f, int s, int r, void* stream, flo
   };
   switch (d.prec) {
     case MDC_FP32: *re = v.x; *im = v.y; break;
-    case MDC_FP16S: *re = hf(w[0] & 0xFFFFu) / sf; *im = hf(w[0] >> 16) / sf; break;
+    case MDC_FP16S:
+    case MDC_FP16: *re = hf(w[0] & 0xFFFFu) / sf; *im = hf(w[0] >> 16) / sf; break;
     case MDC_BF16: *re = bf(w[0] & 0xFFFFu); *im = bf(w[0] >> 16); break;
     case MDC_BF16X2: *re = bf(w[0] & 0xFFFFu) + bf(w[1] & 0xFFFFu); *im = bf(w[0] >> 16) + bf(w[1] >> 16); break;
   }

@@ -13,6 +13,8 @@
 //           frequency); spectra split into FP16 hi + lo of X * 2^s_f, s_f from a
 //           per-frequency maximum; two products on v_mfma_f32_32x32x16_f16; both
 //           scales divided out of the result (exact, powers of two).
+//   FP16:   the FP16S kernel and scales, spectra rounded once to FP16 (the hi part
+//           of the split): one product Khi Xhi.
 //
 // The complex product is the real embedding used by the FP32 kernel: the
 // interleaved kernel is a real ns x 2nr matrix (forward) or its transpose
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
                                                              int tiles_n, int nblocks) {
   __shared__ __attribute__((aligned(16))) unsigned int Bs[3 * BUF];
   constexpr bool X2 = FMT == MDC_BF16X2;
-  constexpr bool F16 = FMT == MDC_FP16S;
+  constexpr bool F16 = FMT == MDC_FP16S || FMT == MDC_FP16;
+  constexpr bool ONE = FMT == MDC_FP16;  // spectra hi part only: one product
   using frag = typename std::conditional<F16, h8v, bf8v>::type;
   constexpr int NA = X2 ? 8 : 4;  // u4v per lane per k-step: 2 row blocks x 2 k-halves x (hi, lo | one)
 
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
     for (int ni = 0; ni < 4; ++ni) {
       const int off = (ni * 32 + l32) * LDB + ks * 16 + 8 * h + 4 * kh;
       F.hi[ni] = __builtin_bit_cast(frag, *reinterpret_cast<const u4v*>(Bh + off));
-      F.lo[ni] = __builtin_bit_cast(frag, *reinterpret_cast<const u4v*>(Bl + off));
+      if constexpr (!ONE) F.lo[ni] = __builtin_bit_cast(frag, *reinterpret_cast<const u4v*>(Bl + off));
     }
   };
 
@@ -215,8 +218,10 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
       const frag ah = __builtin_bit_cast(frag, r[X2 ? 2 * q : q]);
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(ah, F.hi[ni], acc[rb][ni]);
+      if constexpr (!ONE) {
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(ah, F.lo[ni], acc[rb][ni]);
+        for (int ni = 0; ni < 4; ++ni) acc[rb][ni] = mma(ah, F.lo[ni], acc[rb][ni]);
+      }
       if constexpr (X2) {
         const frag al = __builtin_bit_cast(frag, r[2 * q + 1]);
 #pragma unroll
@@ -372,7 +377,7 @@ mdc_status launch_fmt(const mdc_desc& d, const char* K, const float* fscale, int
   const int nblocks = (int)nb;
   float* bmax = reinterpret_cast<float*>(reinterpret_cast<char*>(bsplit) + align_up(split_data_bytes(d), 256));
   const dim3 sgrid((KG * 4 + 63) / 64, NCP / 64, d.nfmax);
-  if constexpr (FMT == MDC_FP16S) {
+  if constexpr (FMT == MDC_FP16S || FMT == MDC_FP16) {
     hipLaunchKernelGGL(zero_floats, dim3((d.nfmax + 255) / 256), dim3(256), 0, st, bmax, d.nfmax);
     const size_t per_f = (size_t)KD * ncols;
     const int bx = (int)std::min<size_t>(64, (per_f + kThreads * 16 - 1) / (kThreads * 16));
@@ -422,6 +427,7 @@ mdc_status gemm16_launch(const mdc_desc& d, const void* K, const float* fscale, 
   const char* k = static_cast<const char*>(K);
   switch (d.prec) {
     case MDC_FP16S: return launch_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
+    case MDC_FP16: return launch_fmt<MDC_FP16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
     case MDC_BF16: return launch_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
     case MDC_BF16X2: return launch_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
     default: return fail(MDC_EINVAL, "gemm16: not a 16-bit format");

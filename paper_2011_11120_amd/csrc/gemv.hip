@@ -308,7 +308,8 @@ mdc_status gemv_launch(const mdc_desc& d, const void* K, const float* fscale, in
   const char* k = static_cast<const char*>(K);
   switch (d.prec) {
     case MDC_FP32: return gemv_fmt<MDC_FP32>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
-    case MDC_FP16S: return gemv_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
+    case MDC_FP16S:  // the spectra stay FP32 here: both FP16 formats take this path
+    case MDC_FP16: return gemv_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
     case MDC_BF16: return gemv_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
     case MDC_BF16X2: return gemv_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, st);
   }

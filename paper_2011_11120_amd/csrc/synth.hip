@@ -129,7 +129,8 @@ mdc_status synth_launch(const mdc_desc& d, const mdc_synth_desc& sd, const Store
       hipLaunchKernelGGL(synth_kernel<StoreBF16X2>, grid, dim3(256), 0, st, a, sd.s_index, sd.r_index,
                          StoreBF16X2(st_ref));
       break;
-    case MDC_FP16S: {
+    case MDC_FP16S:
+    case MDC_FP16: {
       // two passes: per-frequency maxima, power-of-two scales, then the scaled FP16 values
       if (hipMemsetAsync(st_ref.fscale, 0, (size_t)d.nfmax * 4, st) != hipSuccess)
         return fail(MDC_EDEVICE, "clearing the scale table failed");

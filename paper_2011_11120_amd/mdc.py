@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libmdcgpu.so")
 
 MDC_OK, MDC_EINVAL, MDC_ENOMEM, MDC_EDEVICE, MDC_EBUSY, MDC_ENOTREADY, MDC_ECANCELED, MDC_ENOTSUP = \
     0, -1, -2, -3, -4, -5, -6, -7
-MDC_FP32, MDC_FP16S, MDC_BF16, MDC_BF16X2 = 0, 1, 2, 3
+MDC_FP32, MDC_FP16S, MDC_BF16, MDC_BF16X2, MDC_FP16 = 0, 1, 2, 3, 4
 MDC_OP_MDC, MDC_OP_MARCHENKO = 0, 1
-PREC = {"fp32": MDC_FP32, "fp16s": MDC_FP16S, "bf16": MDC_BF16, "bf16x2": MDC_BF16X2}
+PREC = {"fp32": MDC_FP32, "fp16s": MDC_FP16S, "bf16": MDC_BF16, "bf16x2": MDC_BF16X2, "fp16": MDC_FP16}
 
 
 class MdcError(RuntimeError):

@@ -128,7 +128,7 @@ def test_c4_lsqr_residual_identity(mdcmod, c4):
     assert abs(float(res) - h[-1]) < 1e-4 * h[0]            # ||d - M x|| == phibar (exact arithmetic identity)
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "fp16s"])
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "fp16"])
 def test_c4_low_precision_solution_matches_fp32(mdcmod, c4, prec):
     """Full size, 30 iterations: the solution with a 16-bit stored kernel stays within the 1e-3
     relative model error of the FP32 solution (same right-hand side, same onsets)."""

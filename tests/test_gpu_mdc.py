@@ -282,10 +282,10 @@ def test_gemv_forced_for_many_columns(mdcmod, monkeypatch, nv):
 
 # ---------------------------------------------------------------- c3 size ----
 # per-apply max-norm bounds of the storage formats (FP32: the FP32 path's 1e-5)
-C3_TOL = {"fp32": TOL, "bf16x2": 2e-5, "fp16s": 2e-3, "bf16": 8e-3}
+C3_TOL = {"fp32": TOL, "bf16x2": 2e-5, "fp16s": 2e-3, "bf16": 8e-3, "fp16": 2e-3}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp16s", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp16s", "bf16", "fp16"])
 def test_c3_full_size_sampled(mdcmod, prec):
     """nt=1024, nfmax=300, ns=nr=3600, nv=64 on the matrix cores, every storage format; sampled
     (trace, point) pairs of the forward and adjoint against the FP64 oracle."""

@@ -16,7 +16,7 @@ from paper_2011_11120_amd import synth, workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"bf16x2": 2e-5, "fp16s": 2e-3, "bf16": 8e-3}
+TOL = {"bf16x2": 2e-5, "fp16s": 2e-3, "bf16": 8e-3, "fp16": 2e-3}
 
 
 def relmax(a, b):
@@ -46,7 +46,7 @@ SHAPES = [(64, 20, 40, 40, 1), (128, 40, 130, 98, 3), (128, 40, 129, 257, 9),
           (256, 60, 300, 200, 64), (128, 30, 200, 130, 65), (64, 20, 70, 30, 17)]
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16"])
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16", "fp16"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_formats_match_oracle(mdcmod, prec, shape):
     nt, nfmax, ns, nr, nv = shape
@@ -63,9 +63,10 @@ def test_formats_match_oracle(mdcmod, prec, shape):
     op.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16"])
-def test_formats_dot_product(mdcmod, prec):
-    """The forward and adjoint read the same stored kernel, so the pair stays adjoint."""
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp16s", 1e-5), ("bf16", 1e-5), ("fp16", 2.0 ** -11)])
+def test_formats_dot_product(mdcmod, prec, tol):
+    """The forward and adjoint read the same stored kernel, so the pair stays adjoint; with FP16
+    spectra (one product) only up to the rounding of the spectra, 2^-11 relative."""
     nt, nfmax, ns, nr, nv = 128, 40, 150, 90, 12
     K = synth.random_complex_kernel(nfmax, ns, nr, seed=1)
     op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
@@ -74,10 +75,12 @@ def test_formats_dot_product(mdcmod, prec):
     y = synth.gaussian((nt, ns, nv), seed=6)
     lhs = np.vdot(host(op.forward(dev(x))), y)
     rhs = np.vdot(x, host(op.adjoint(dev(y))))
-    assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+    print(f"dot test {prec}: {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+    assert abs(lhs - rhs) < tol * abs(lhs)
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x2", 2.0 ** -15), ("fp16s", 2.0 ** -10), ("bf16", 2.0 ** -7)])
+@pytest.mark.parametrize("prec,tol", [("bf16x2", 2.0 ** -15), ("fp16s", 2.0 ** -10), ("bf16", 2.0 ** -7),
+                                      ("fp16", 2.0 ** -10)])
 def test_generator_formats(mdcmod, prec, tol):
     spec = synth.KernelSpec(nt=256, nfmax=60, nx=12)
     op = mdcmod.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, prec=prec)
@@ -91,7 +94,7 @@ def test_generator_formats(mdcmod, prec, tol):
     op.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x2", "fp16s"])
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "fp16"])
 def test_marchenko_lsqr_low_precision(mdcmod, prec):
     case = workloads.marchenko_case(nx=12, nt=256, nfmax=70, d=1, px=4, py=4,
                                     kappa_value=workloads.kappa("c4") * 8.0)
