@@ -365,7 +365,11 @@ class Server:
 
 # ------------------------------------------------------------ convenience ----
 class MdcOp:
-    """Owns the device buffers (PyTorch) of one operator and its library handle."""
+    """Owns the device buffers (PyTorch) of one operator and its library handle.
+
+    prec: storage format of the resident kernel, one of PREC's names ("fp32", "fp16s",
+    "bf16", "bf16x2", "fp16") or an mdc_prec value.
+    """
 
     def __init__(self, nt, nfmax, ns, nr, max_cols=1, prec="fp32", device="cuda"):
         self.desc = mdc_desc(nt, nfmax, ns, nr, max_cols, PREC[prec] if isinstance(prec, str) else prec)
