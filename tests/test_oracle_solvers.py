@@ -132,6 +132,61 @@ def test_neumann_series_equals_lsqr_solution():
     assert rel(r[0], d[0]) < 1e-10
 
 
+def _block_parts(nt=16, nx=2, nv=1):
+    """Time-domain R and R* matrices (entry by entry) of the case, with Theta as a diagonal."""
+    k, K, onset = _marchenko_case(nt, nx=nx, nv=nv)
+    R = _conv_matrix(k)
+    Rs = _conv_matrix(np.roll(k[::-1], 1, axis=0))  # R*: correlation = convolution with k(-t)
+    return k, K, onset, R, Rs
+
+
+def test_greens_match_dense_eq6_block_matrix():
+    """Eq.6 with f- != 0: [-g-; g+*] = [[I, -R], [-R*, I]] [f-; f+], R and R* assembled entry by entry."""
+    nt = 16
+    k, K, onset, R, Rs = _block_parts(nt)
+    n = k.shape[1]
+    I = np.eye(nt * n)
+    B = np.block([[I, -R], [-Rs, I]])
+    fm = synth.gaussian((nt, n, 1), seed=21)
+    fplus = synth.gaussian((nt, n, 1), seed=22)
+    gm, gpc = om.greens(K, fm, fplus)
+    lhs = B @ np.concatenate([fm.ravel(), fplus.ravel()])
+    assert rel(-gm.ravel(), lhs[: nt * n]) < 1e-12
+    assert rel(gpc.ravel(), lhs[nt * n:]) < 1e-12
+    # the two blocks use different operators: R and R* differ for this kernel, so swapping them,
+    # or dropping the f- terms, changes the result well beyond rounding
+    assert rel(R @ fplus.ravel(), Rs @ fplus.ravel()) > 0.1
+    assert rel(-gm.ravel(), (fm.ravel() - Rs @ fplus.ravel())) > 0.1
+    assert rel(gpc.ravel(), fplus.ravel() - R @ fm.ravel()) > 0.1
+    assert rel(gpc.ravel(), fplus.ravel()) > 0.1
+
+
+def test_marchenko_data_matches_dense_theta_r():
+    """Right-hand side of Eq.5: (Theta R f_d+, 0) from the entry-by-entry convolution matrix."""
+    nt = 16
+    k, K, onset, R, Rs = _block_parts(nt)
+    n = k.shape[1]
+    th = om.theta(nt, onset)
+    fd = synth.ricker_spikes(nt, n, 1)
+    d0, d1 = om.data(K, onset, fd)
+    ref = th[:, :, 0].ravel() * (R @ fd.ravel())
+    assert rel(d0.ravel(), ref) < 1e-12
+    assert np.all(d1 == 0) and d1.shape == fd.shape
+    # the window removes part of the product and R* differs from R on this input
+    assert rel(d0.ravel(), R @ fd.ravel()) > 0.1
+    assert rel(d0.ravel(), th[:, :, 0].ravel() * (Rs @ fd.ravel())) > 0.1
+
+
+@pytest.mark.parametrize("shape,scale", [((12, 12), 3.7), ((9, 14), 0.21), ((20, 7), 11.0)])
+def test_spectral_norm_matches_svd(shape, scale):
+    """Power iteration on K^H K returns the largest singular value (not its square)."""
+    from oracle import power
+    K = scale * (synth.gaussian(shape, seed=41) + 1j * synth.gaussian(shape, seed=42))
+    ref = np.linalg.norm(K, 2)
+    assert abs(ref - 1.0) > 0.5  # so that the norm and its square differ
+    assert abs(power.spectral_norm(K, iters=400) - ref) < 1e-9 * ref
+
+
 def test_greens_single_scattering():
     """Eq.6 with f- = 0 and f+ = f_d+ gives g- = R f_d+ (single-scattering redatuming)."""
     nt = 32
