@@ -16,7 +16,8 @@ import numpy as np
 
 from . import synth
 
-_KAPPA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden", "kappa.json")
+# Package data: the synthetic kernel scales, written by tests/golden/make_kappa.py.
+_KAPPA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "kappa.json")
 
 
 def kappa(name: str) -> float:

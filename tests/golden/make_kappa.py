@@ -1,4 +1,4 @@
-"""Write tests/golden/kappa.json: the scale of the synthetic reflection kernels.
+"""Write paper_2011_11120_amd/data/kappa.json: the scale of the synthetic reflection kernels.
 
 The Marchenko operator M = [[I, -Theta R], [-Theta R*, I]] (Eq.5) is well
 conditioned when every slice has ||K_f||_2 <= q < 1 (sigma(M) in [1-q, 1+q]).
@@ -6,7 +6,8 @@ For the 2500-trace workload the spectral norm of sampled slices is taken with
 the FP64 oracle's power iteration on host-generated slices; for the
 10000-trace workload (too large to generate on the host) the Frobenius norm
 of sampled rows bounds the spectral norm from above.  Only the seeded input
-generator and oracle.power are used.
+generator and oracle.power are used.  The value is an input parameter of the
+workload generators, so it is stored as package data, not as a test fixture.
 
     python tests/golden/make_kappa.py
 """
@@ -58,6 +59,7 @@ def c5(ratio):
 if __name__ == "__main__":
     a = c4()
     out = {"c4": a, "c5": c5(a["spectral_over_frobenius_max"])}
-    with open(os.path.join(HERE, "kappa.json"), "w") as fh:
+    dst = os.path.join(os.path.dirname(os.path.dirname(HERE)), "paper_2011_11120_amd", "data", "kappa.json")
+    with open(dst, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps({k: v["kappa"] for k, v in out.items()}))
