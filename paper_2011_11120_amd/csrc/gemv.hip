@@ -260,7 +260,7 @@ mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int
   constexpr int VEC = KF<FMT>::VEC;
   if (!adjoint) {
     constexpr int RW = (NC * VEC >= 16) ? 2 : 4;
-    const int rc = 4096 / NC;
+    const int rc = (4096 / NC) & ~3;  // chunk of the reduction held in LDS, a multiple of 4
     const int rows_per_group = kWaves * RW;
     const int ngroups = (d.ns + rows_per_group - 1) / rows_per_group;
     int gpb = (int)((long)ngroups * d.nfmax / 4096);
@@ -287,22 +287,30 @@ mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int
 template <int FMT>
 mdc_status gemv_fmt(const mdc_desc& d, const char* K, const float* fscale, int ldk, int adjoint, const float2* in,
                     float2* out, int ncols, hipStream_t st) {
+  // one pass over the kernel for every group of up to 8 columns (any width below 9 reads K once)
   int c0 = 0;
   while (c0 < ncols) {
-    const int rem = ncols - c0;
+    const int nc = ncols - c0 >= 8 ? 8 : ncols - c0;
     mdc_status s;
-    if (rem >= 8) { s = gemv_group<FMT, 8>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 8; }
-    else if (rem >= 4) { s = gemv_group<FMT, 4>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 4; }
-    else if (rem >= 2) { s = gemv_group<FMT, 2>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 2; }
-    else { s = gemv_group<FMT, 1>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); c0 += 1; }
+    switch (nc) {
+      case 8: s = gemv_group<FMT, 8>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 7: s = gemv_group<FMT, 7>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 6: s = gemv_group<FMT, 6>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 5: s = gemv_group<FMT, 5>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 4: s = gemv_group<FMT, 4>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 3: s = gemv_group<FMT, 3>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      case 2: s = gemv_group<FMT, 2>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+      default: s = gemv_group<FMT, 1>(d, K, fscale, ldk, adjoint, in, out, ncols, c0, st); break;
+    }
     if (s != MDC_OK) return s;
+    c0 += nc;
   }
   return MDC_OK;
 }
 
 }  // namespace
 
-// Few-column product (ncols columns in groups of 8, 4, 2, 1), any storage format.
+// Few-column product (ncols columns in groups of at most 8, one kernel pass each), any storage format.
 mdc_status gemv_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint, const float2* in,
                        float2* out, int ncols, hipStream_t st) {
   const char* k = static_cast<const char*>(K);

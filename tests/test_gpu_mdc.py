@@ -73,7 +73,9 @@ SHAPES = [
     (1024, 60, 70, 130, 4),
     (2048, 30, 20, 32, 1),
     (64, 33, 40, 40, 8),
-    (64, 20, 40, 40, 13),       # 8 + 4 + 1 column groups
+    (64, 20, 40, 40, 13),       # 8 + 5 column groups
+    (128, 30, 70, 94, 6),       # one streaming pass of 6 columns
+    (64, 20, 45, 37, 7),        # one streaming pass of 7 columns, odd nr
     (64, 25, 25, 25, 1),        # odd nr: padded rows
     (128, 40, 31, 129, 3),      # odd nr, ragged column tile
     (128, 30, 90, 258, 5),

@@ -63,6 +63,25 @@ def test_formats_match_oracle(mdcmod, prec, shape):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp16s", "bf16"])
+@pytest.mark.parametrize("nv", [3, 5, 6, 7])
+def test_streaming_widths_match_oracle(mdcmod, monkeypatch, prec, nv):
+    """Every width below 9 streams the kernel once, for every storage format."""
+    monkeypatch.setenv("MDC_PRODUCT", "gemv")
+    nt, nfmax, ns, nr = 128, 30, 75, 133
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=7 * nv)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    x = synth.gaussian((nt, nr, nv), seed=8)
+    y = synth.gaussian((nt, ns, nv), seed=9)
+    ef = relmax(host(op.forward(dev(x))), om.mdc_forward(K, x))
+    ea = relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y))
+    tol = 1e-5 if prec == "fp32" else TOL[prec]
+    print(f"streaming {prec} nv={nv}: forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef < tol and ea < tol
+    op.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp16s", 1e-5), ("bf16", 1e-5), ("fp16", 2.0 ** -11)])
 def test_formats_dot_product(mdcmod, prec, tol):
     """The forward and adjoint read the same stored kernel, so the pair stays adjoint; with FP16
