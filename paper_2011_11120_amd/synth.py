@@ -24,7 +24,9 @@ published definition independently; tests compare sampled elements.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -222,7 +224,9 @@ def kernel_block(spec: KernelSpec, f_idx, s_idx, r_idx) -> np.ndarray:
     out = np.empty((f_idx.size, s_idx.size, r_idx.size), dtype=np.complex128)
     n = spec.n
     rms = math.sqrt(float(np.sum(ev.amp ** 2)))
-    for i, f in enumerate(f_idx):
+
+    def one_bin(i):
+        f = f_idx[i]
         ff = f / (spec.nt * spec.dt)
         wf = spec.kappa * spec.dA * float(ricker_spectrum(ff, spec.fp))
         acc = np.zeros((s_idx.size, r_idx.size), dtype=np.complex128)
@@ -236,6 +240,16 @@ def kernel_block(spec: KernelSpec, f_idx, s_idx, r_idx) -> np.ndarray:
         n2 = rng_normal(spec.seed, STREAM_KNOISE, q * np.uint64(2) + np.uint64(1))
         sig = spec.noise * wf * rms / math.sqrt(2.0)
         out[i] = wf * acc + sig * (n1 + 1j * n2)
+
+    # bins are independent; numpy releases the GIL inside these array expressions, so large
+    # blocks are generated by a few threads (the values do not depend on the thread count)
+    workers = min(16, os.cpu_count() or 1, f_idx.size) if s_idx.size * r_idx.size >= 1 << 16 else 1
+    if workers > 1:
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one_bin, range(f_idx.size)))
+    else:
+        for i in range(f_idx.size):
+            one_bin(i)
     return out
 
 

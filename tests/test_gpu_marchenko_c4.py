@@ -5,7 +5,11 @@ iterate for iterate (FP32 vectors, FP64 scalars: tolerance 1e-5 on the
 solution).  Full size (nt=1024, nfmax=250, 50 x 50 traces, nv=32): the
 Marchenko apply is compared on sampled (trace, point) pairs, the operator
 passes the dot-product test, and the solve satisfies the LSQR identity
-||d - M x|| = phibar.
+||d - M x|| = phibar.  On the 4x decimated full-size grid (626 traces, the
+same 32 points and 30 iterations) the whole solve is compared with the FP64
+oracle's LSQR in every storage format: FP32 to 1e-5, the 16-bit formats to
+the 1e-3 model-error budget, with the phibar history checked iterate by
+iterate.
 """
 import numpy as np
 import pytest
@@ -147,3 +151,50 @@ def test_c4_low_precision_solution_matches_fp32(mdcmod, c4, prec):
     h = hist.cpu().numpy()
     assert h[-1] < 1e-2 * h[0]
     lp.close()
+
+
+@pytest.fixture(scope="module")
+def c4d4_oracle():
+    """FP64 oracle LSQR on the 4x decimated full-size Marchenko problem (host, about a minute)."""
+    import time
+    case = workloads.marchenko_case(d=4, kappa_value=workloads.kappa("c4"))
+    t0 = time.perf_counter()
+    K = synth.kernel_block(case.spec, np.arange(case.spec.nfmax), case.idx, case.idx)
+    Kc = np.conj(K)
+    print(f"c4 d4 oracle: kernel {K.shape} generated in {time.perf_counter() - t0:.1f} s", flush=True)
+    th = omc.theta(case.spec.nt, case.onset)
+    # the oracle's Marchenko blocks (Eq.5) with the conjugated kernel formed once
+    fwd = lambda v: [v[0] - th * om.mdc_forward(K, v[1]), -th * om.mdc_forward(Kc, v[0]) + v[1]]
+    adj = lambda u: [u[0] - om.mdc_adjoint(Kc, th * u[1]), -om.mdc_adjoint(K, th * u[0]) + u[1]]
+    calls = [0]
+
+    def fwd_p(v):
+        calls[0] += 1
+        if calls[0] % 5 == 0:
+            print(f"c4 d4 oracle: iteration {calls[0]} of 30 ({time.perf_counter() - t0:.0f} s)", flush=True)
+        return fwd(v)
+
+    d0, d1 = omc.data(K, case.onset, case.fd)
+    xr, hr = ol.lsqr(fwd_p, adj, [d0, d1], 30)
+    print(f"c4 d4 oracle: done in {time.perf_counter() - t0:.1f} s, phibar {hr[0]:.3e} -> {hr[-1]:.3e}", flush=True)
+    return case, d0, np.stack(xr), hr
+
+
+@pytest.mark.parametrize("prec,tol_data,tol", [("fp32", 1e-5, 1e-5), ("fp16s", 2e-3, 1e-3), ("bf16x2", 2e-5, 1e-3)])
+def test_c4_d4_full_size_lsqr_matches_oracle(mdcmod, c4d4_oracle, prec, tol_data, tol):
+    case, d0, xr, hr = c4d4_oracle
+    print(f"c4 d4 {prec}: n={case.n} nv={case.nv}", flush=True)
+    op = mdcmod.MdcOp(case.spec.nt, case.spec.nfmax, case.n, case.n, max_cols=2 * case.nv, prec=prec)
+    op.synth_kernel(case.spec, s_index=case.idx, r_index=case.idx)
+    on = dev(case.onset, torch.int32)
+    dg = op.marchenko_data(on, dev(case.fd))
+    e_data = relmax(dg[0].cpu().numpy().astype(np.float64), d0)
+    x, hist = op.lsqr(dg, 30, kind=mdcmod.MDC_OP_MARCHENKO, nv=case.nv, onset=on)
+    err = rel2(x.cpu().numpy().astype(np.float64), xr)
+    eh = float(np.max(np.abs(hist.cpu().numpy() - hr)) / hr[0])
+    print(f"c4 d4 {prec}: data {e_data:.2e}, model error {err:.2e}, phibar history {eh:.2e}", flush=True)
+    assert e_data < tol_data
+    assert err < tol
+    assert eh < tol
+    assert hr[-1] < 1e-2 * hr[0]
+    op.close()
