@@ -27,6 +27,13 @@
  * so applies on the same op must be issued in order on one stream; distinct
  * ops (each with its own workspace) may run concurrently.
  *
+ * Alignment: buffers the library carves into pieces (resident, workspace, the
+ * solver work buffers, the serving arena) must be 256-byte aligned.  Vector
+ * arguments need only element (4-byte) alignment: the transforms move four
+ * traces per 16-byte access when the pointer and the trace count allow it and
+ * fall back to element accesses otherwise, and the Marchenko solvers pass the
+ * second block of a vector as an element offset into the first.
+ *
  * Errors: every function returns an mdc_status; nothing throws.  On error
  * no work has been enqueued (argument checks run first) except for
  * MDC_EDEVICE, which reports a failed launch.  mdc_last_error() returns a
@@ -70,7 +77,11 @@ typedef enum {
  *   MDC_FP16   the MDC_FP16S kernel; on the matrix cores the spectra are rounded
  *              once to FP16 (power-of-two scale per frequency) instead of split
  *              into hi + lo, so the product takes one pass instead of two (about
- *              2^-11 relative error per apply instead of 2^-12).  */
+ *              2^-11 relative error per apply instead of 2^-12).  Forward and
+ *              adjoint round different spectra, so on the matrix cores this
+ *              format is adjoint only up to that rounding (dot-product test
+ *              about 1e-4, against 1e-6 for the other formats); an iterative
+ *              solver on it converges to a slightly perturbed normal equation.  */
 typedef enum { MDC_FP32 = 0, MDC_FP16S = 1, MDC_BF16 = 2, MDC_BF16X2 = 3, MDC_FP16 = 4 } mdc_prec;
 
 typedef struct mdc_op mdc_op;
@@ -279,6 +290,13 @@ typedef struct {
   double c;          /* direct-arrival velocity (m/s) */
   int eps;           /* window margin in samples */
   double fp;         /* peak frequency of the initial focusing wavelet (Hz) */
+  int sublattice;    /* decimation levels solved on their own lattice: 0, 2, 4 or 2|4.  For such
+                        a level serve_create gathers the lattice's kernel rows and columns once
+                        into the arena (serve_level_bytes), and its requests run their
+                        transforms, product and Krylov vectors on the lattice's traces only
+                        (the Sub2 / Sub4 problems of Table 1: 1/d of the traces, 1/d^2 of the
+                        kernel).  Other decimated requests run on the full grid with zero
+                        traces off the lattice. */
 } serve_geometry;
 typedef struct {
   int nv;                  /* focusing points, 1..64 */
@@ -289,15 +307,21 @@ typedef struct {
   double* hist;            /* device [niter+1] residual-norm history, or NULL */
 } serve_req;
 
-/* Arena bytes one request of nv points occupies. */
+/* Arena bytes one request of nv points occupies on the full grid (an upper bound for lattice
+ * levels, whose slots hold four vectors of 1/d the length instead of three full ones). */
 mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes);
+/* Arena bytes serve_create reserves for the lattice level of decimation 2 or 4 (index tables
+ * and the gathered kernel in the op's storage format). */
+mdc_status serve_level_bytes(const mdc_op* op, int decim, size_t* bytes);
 /* arena: caller-owned device buffer (256-byte aligned) for request slots. */
 mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t arena_bytes, mdc_server** out);
 /* Queue a request (MDC_ENOMEM if it can never fit the arena or the column budget). Buffers
  * must be ready (their producers synchronised) before the call. */
 mdc_status serve_submit(mdc_server* srv, const serve_req* req, uint64_t* id);
 /* done = 1 and MDC_OK when finished (latency = completion - submission, seconds);
- * done = 0 and MDC_ENOTREADY while queued or running; done = -1 and MDC_ECANCELED. */
+ * done = 0 and MDC_ENOTREADY while queued or running; done = -1 and MDC_ECANCELED.  A finished
+ * request is reported once: the server then releases it, and a later poll or cancel of the
+ * same id returns MDC_EINVAL (unknown id), so a long-running server holds only live requests. */
 mdc_status serve_poll(mdc_server* srv, uint64_t id, int* done, double* latency_s);
 /* Cancel a queued or running request; it leaves at the next step boundary. */
 mdc_status serve_cancel(mdc_server* srv, uint64_t id);
@@ -308,13 +332,20 @@ mdc_status serve_drain(mdc_server* srv);
  * largest number of simultaneously admitted requests, and the number of steps run. */
 mdc_status serve_stats(mdc_server* srv, int skip, double* solves_per_s, double* p50_s, double* p99_s,
                        int* completed, int* max_active, long* steps);
-/* Stop the worker (cancelling what is left) and release the handle. */
+/* Lockstep phases.  Every admitted request applies the operator in the step's direction and new
+ * requests (which start with a forward application) join at forward steps, so each pass over
+ * the kernel serves every admitted request.  request_steps: requests served, summed over steps;
+ * deferred: requests that could have been admitted during an adjoint step and waited for it;
+ * deferred_s: the time they waited, summed (the latency a pass serving both directions at once
+ * would remove). */
+mdc_status serve_phase_stats(mdc_server* srv, long* request_steps, long* deferred, double* deferred_s);
 /* Steps captured into hipGraphs and steps replayed from them so far.  Within a fixed set
  * of active requests every forward and every adjoint step enqueues the same launches: the
  * first step of such a composition runs eagerly, the second is captured, later ones replay
  * the graph (environment MDC_SERVE_GRAPH=0 runs every step eagerly). */
 mdc_status serve_graph_stats(mdc_server* srv, long* captured, long* replayed);
 
+/* Stop the worker (cancelling what is left) and release the handle. */
 mdc_status serve_destroy(mdc_server* srv);
 
 #ifdef __cplusplus

@@ -68,12 +68,18 @@ static mdc_status run_family(const mdc_op* op, int fam, int adjoint, const float
   return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, op->bsplit, st);
 }
 
-int choose_family(const mdc_op* op, int adjoint, int ncols) {
+int forced_family(const mdc_op* op) {
   if (const char* e = getenv("MDC_PRODUCT")) {  // forced family (tests)
     if (!strcmp(e, "gemv")) return kFamGemv;
     if (!strcmp(e, "gemm")) return kFamGemm64;
     if (!strcmp(e, "gemm32")) return op->d.prec == MDC_FP32 ? kFamGemm32 : kFamGemm64;
   }
+  return -1;
+}
+
+int choose_family(const mdc_op* op, int adjoint, int ncols) {
+  const int forced = forced_family(op);
+  if (forced >= 0) return forced;
   const auto& ns = op->tune_ncols;
   if (!ns.empty()) {
     size_t i = 0;
@@ -403,9 +409,101 @@ mdc_status apply_neumann(mdc_op* op, const int* onset, int nv, const float* dvec
   return check_launch("neumann");
 }
 
+// Kernel of a sub-grid: dst[f][i][j] = src[f][idx[i]][idx[j]] for i, j < nsub (pad columns zero),
+// copied word for word in the storage format.  KIND 0: 8-byte elements (complex64), 1: 4-byte
+// pairs (FP16S, FP16, BF16), 2: BF16 hi + lo rows stored in groups of four complex values.
+template <int KIND>
+__global__ void gather_sub_kernel(const unsigned int* __restrict__ src, unsigned int* __restrict__ dst,
+                                  const int* __restrict__ idx, int nfmax, int ns, int ldk, int nsub, int ldks) {
+  const size_t count = (size_t)nfmax * nsub * ldks;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = e / (size_t)ldks;
+    const int j = (int)(e - row * (size_t)ldks);
+    const int f = (int)(row / (size_t)nsub), i = (int)(row - (size_t)f * nsub);
+    const bool in = j < nsub;
+    const size_t srow = (size_t)f * ns + idx[i];
+    const int r = in ? idx[j] : 0;
+    if constexpr (KIND == 0) {
+      const uint2 v = in ? reinterpret_cast<const uint2*>(src)[srow * ldk + r] : make_uint2(0u, 0u);
+      reinterpret_cast<uint2*>(dst)[row * ldks + j] = v;
+    } else if constexpr (KIND == 1) {
+      dst[row * ldks + j] = in ? src[srow * ldk + r] : 0u;
+    } else {
+      const unsigned int* sr = src + srow * (size_t)ldk * 2;
+      unsigned int* dr = dst + row * (size_t)ldks * 2;
+      const int gs = (r >> 2) * 8 + (r & 3), gd = (j >> 2) * 8 + (j & 3);
+      dr[gd] = in ? sr[gs] : 0u;
+      dr[gd + 4] = in ? sr[gs + 4] : 0u;
+    }
+  }
+}
+
 }  // namespace
 
 namespace mdc {
+
+size_t sub_op_resident_bytes(const mdc_op* parent, int nsub) {
+  mdc_desc d = parent->d;
+  d.ns = d.nr = nsub;
+  return layout_of(d).resident;
+}
+
+mdc_status sub_op_create(const mdc_op* parent, const int* idx, int nsub, void* resident, hipStream_t st,
+                         mdc_op** out) {
+  const mdc_desc& pd = parent->d;
+  if (pd.ns != pd.nr || nsub < 1 || nsub > pd.ns) return fail(MDC_EINVAL, "sub-grid of %d traces", nsub);
+  if (!resident || !aligned(resident, kAlign)) return fail(MDC_EINVAL, "sub-grid resident must be 256-byte aligned");
+  mdc_desc d = pd;
+  d.ns = d.nr = nsub;
+  const Layout L = layout_of(d);
+  mdc_op* op = new (std::nothrow) mdc_op();
+  if (!op) return fail(MDC_ENOMEM, "host allocation failed");
+  op->d = d;
+  op->resident = static_cast<char*>(resident);
+  op->work = parent->work;  // every piece of the sub-grid workspace fits in the parent's
+  op->tw = reinterpret_cast<float2*>(op->resident + L.tw);
+  op->fscale = reinterpret_cast<float*>(op->resident + L.fscale);
+  op->kstore = op->resident + L.kstore;
+  op->specR = reinterpret_cast<float2*>(op->work + L.specR);
+  op->specS = reinterpret_cast<float2*>(op->work + L.specS);
+  op->bsplit = d.prec != MDC_FP32 ? reinterpret_cast<unsigned int*>(op->work + L.bsplit) : nullptr;
+  op->prof = false;
+  op->tw_host = parent->tw_host;
+  op->tune_ncols = parent->tune_ncols;
+  op->tune_family[0] = parent->tune_family[0];
+  op->tune_family[1] = parent->tune_family[1];
+  bool ok = hipMemcpyAsync(op->tw, parent->tw, (size_t)d.nt * sizeof(float2), hipMemcpyDeviceToDevice, st) ==
+                hipSuccess &&
+            hipMemcpyAsync(op->fscale, parent->fscale, (size_t)d.nfmax * 4, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (!ok) {
+    delete op;
+    return fail(MDC_EDEVICE, "copying the sub-grid tables failed");
+  }
+  const unsigned int* src = static_cast<const unsigned int*>(parent->kstore);
+  unsigned int* dst = static_cast<unsigned int*>(op->kstore);
+  const int ldk = kernel_ld(pd.nr), ldks = kernel_ld(nsub);
+  const dim3 grid(4096), block(256);
+  switch (d.prec) {
+    case MDC_FP32:
+      hipLaunchKernelGGL(gather_sub_kernel<0>, grid, block, 0, st, src, dst, idx, d.nfmax, pd.ns, ldk, nsub, ldks);
+      break;
+    case MDC_BF16X2:
+      hipLaunchKernelGGL(gather_sub_kernel<2>, grid, block, 0, st, src, dst, idx, d.nfmax, pd.ns, ldk, nsub, ldks);
+      break;
+    default:
+      hipLaunchKernelGGL(gather_sub_kernel<1>, grid, block, 0, st, src, dst, idx, d.nfmax, pd.ns, ldk, nsub, ldks);
+      break;
+  }
+  const mdc_status s = check_launch("gather_sub_kernel");
+  if (s != MDC_OK) {
+    delete op;
+    return s;
+  }
+  op->kernel_ready = parent->kernel_ready;
+  *out = op;
+  return MDC_OK;
+}
+
 mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld);
 size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld);
 mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
@@ -672,6 +770,7 @@ mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* m
           op->tune_ncols = nc;
           op->tune_family[0] = fw;
           op->tune_family[1] = ad;
+          op->tune_gen += 1;
           found = true;
         }
       }
@@ -706,6 +805,7 @@ mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* m
   op->tune_ncols = nc;
   op->tune_family[0] = best[0];
   op->tune_family[1] = best[1];
+  op->tune_gen += 1;
   if (measured) *measured = 1;
   if (cache_path) {
     if (FILE* fh = fopen(cache_path, "a")) {

@@ -9,12 +9,14 @@
 #include "../../include/mdc.h"
 
 // What a captured LSQR iteration graph depends on (pointers are baked into its nodes).
+// The product family of every apply is fixed at capture time, so the key also holds the
+// tuning-table generation and the forced-family switch.
 struct LsqrGraphKey {
-  int kind, nv, fused;
+  int kind, nv, fused, tune_gen, forced;
   const void *onset, *work, *x, *hist, *b;
   bool operator==(const LsqrGraphKey& o) const {
-    return kind == o.kind && nv == o.nv && fused == o.fused && onset == o.onset && work == o.work && x == o.x &&
-           hist == o.hist && b == o.b;
+    return kind == o.kind && nv == o.nv && fused == o.fused && tune_gen == o.tune_gen && forced == o.forced &&
+           onset == o.onset && work == o.work && x == o.x && hist == o.hist && b == o.b;
   }
 };
 
@@ -39,6 +41,7 @@ struct mdc_op {
   // product family per column bucket and direction (filled by mdc_autotune)
   std::vector<int> tune_ncols;
   std::vector<int> tune_family[2];
+  int tune_gen = 0;  // bumped whenever the table changes
   // LSQR iteration graph (captured on cap_stream, replayed on the caller's stream)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t lsqr_exec = nullptr;
@@ -133,6 +136,16 @@ int irfft_blocks(int nt, int n, int nv);
 // adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].  The kernel family comes from the
 // op's tuning table (mdc_autotune), else from the default crossover.
 mdc_status product_launch(const mdc_op* op, int adjoint, const float2* in, float2* out, int ncols, hipStream_t st);
+// Product family forced by the environment (MDC_PRODUCT = gemv | gemm | gemm32), or -1.
+int forced_family(const mdc_op* op);
+
+// Operator on a sub-grid of a square operator (rows and columns idx, nsub traces): its kernel is
+// gathered from the parent's resident kernel into `resident` (sub_op_resident_bytes) on `st`, the
+// tables and tuning are copied, and the parent's workspace is shared, so applies of the two must
+// not overlap.  Released with mdc_destroy.
+size_t sub_op_resident_bytes(const mdc_op* parent, int nsub);
+mdc_status sub_op_create(const mdc_op* parent, const int* idx, int nsub, void* resident, hipStream_t st,
+                         mdc_op** out);
 
 // Device state of one LSQR solve (all pointers are device memory).
 struct LsqrState {

@@ -387,7 +387,7 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   }
   // Capture one iteration (identical launches every time: the iteration counter lives on the
   // device) on the op's private stream, then replay it on the caller's stream.
-  const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, ld.onset, work, x, hist, b};
+  const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, op->tune_gen, forced_family(op), ld.onset, work, x, hist, b};
   if (!op->lsqr_exec || !(op->lsqr_key == key)) {
     if (op->lsqr_exec) {
       hipGraphExecDestroy(op->lsqr_exec);

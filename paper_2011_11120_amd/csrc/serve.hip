@@ -19,9 +19,17 @@
 //     arena footprint and column budget; results of a request depend only on
 //     its own columns.
 //
-// Decimation by d is carried on the full grid: traces outside the lattice mask
-// have zero inputs, zero window, a zero keep mask on adjoint outputs, and R is
-// scaled by d (areal element d dx^2), which equals the decimated problem.
+// A request decimated by d solves the problem of its lattice (the Sub2 / Sub4
+// geometries of Table 1, areal element d dx^2) in one of two ways:
+//   * on a sub-grid level prepared at creation: the lattice's traces only, with
+//     the kernel rows and columns of the lattice gathered once into the arena, so
+//     the request's product, transforms and vectors all shrink by d (d^2 fewer
+//     kernel multiply-adds per column); its solution is scattered back onto the
+//     full grid (zeros elsewhere) when it finishes;
+//   * on the full grid: traces outside the lattice have zero inputs, zero window
+//     and a zero keep mask on adjoint outputs, which equals the decimated
+//     problem but pays the full-grid product.
+// Requests of different levels share a step; each level runs its own product.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -54,20 +62,22 @@ __device__ __forceinline__ bool lattice_keep(int r, int nx, int d) {
   return true;
 }
 
-// onset[r][v] = max(rint(td/dt) - eps, 0) on kept traces, 0 elsewhere; keep[r][v] = nt or 0;
-// fd[t][r][v] = ricker(lag(t) dt + td) on kept traces, 0 elsewhere; td = |x_r - x_v| / c (FP64,
+// Trace i of the request's problem is full-grid trace idx[i] (a lattice level) or i (the full
+// grid, n = nx^2, traces off the lattice of d masked out).
+// onset[i][v] = max(rint(td/dt) - eps, 0) on kept traces, 0 elsewhere; keep[i][v] = nt or 0;
+// fd[t][i][v] = ricker(lag(t) dt + td) on kept traces, 0 elsewhere; td = |x_r - x_v| / c (FP64,
 // no contraction, so the integer onsets match a host computation exactly).
 __global__ __launch_bounds__(kThreads) void request_inputs(int nt, int nx, double dx, double dt, double c, int eps,
-                                                           double fp, int d, int nv, PointArgs P,
-                                                           int* __restrict__ onset, int* __restrict__ keep,
-                                                           float* __restrict__ fd) {
-  const int n = nx * nx;
+                                                           double fp, int d, int n, const int* __restrict__ idx,
+                                                           int nv, PointArgs P, int* __restrict__ onset,
+                                                           int* __restrict__ keep, float* __restrict__ fd) {
   const size_t Q = (size_t)n * nv;
   for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < (size_t)nt * Q; e += (size_t)gridDim.x * kThreads) {
     const int t = (int)(e / Q);
     const size_t q = e - (size_t)t * Q;
-    const int r = (int)(q / nv), v = (int)(q - (size_t)r * nv);
-    const bool kept = lattice_keep(r, nx, d);
+    const int i = (int)(q / nv), v = (int)(q - (size_t)i * nv);
+    const int r = idx ? idx[i] : i;
+    const bool kept = idx ? true : lattice_keep(r, nx, d);
     const double rx = (double)(r / nx) * dx, ry = (double)(r % nx) * dx;
     const double ax = __dadd_rn(rx, -P.vx[v]), ay = __dadd_rn(ry, -P.vy[v]);
     const double h2 = __dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(P.vz[v], P.vz[v]));
@@ -93,11 +103,39 @@ __global__ void zero_f32(float* __restrict__ p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
+// out[b][t][r][v] = x[b][t][pos[r]][v] where the full-grid trace r is on the lattice (pos[r] >= 0),
+// 0 elsewhere: a lattice solution [2][nt][nsub][nv] written onto the full grid [2][nt][n][nv].
+__global__ __launch_bounds__(kThreads) void scatter_lattice(const float* __restrict__ x, float* __restrict__ out,
+                                                            const int* __restrict__ pos, int nt, int n, int nsub,
+                                                            int nv) {
+  const size_t total = 2ull * nt * n * nv;
+  for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < total; e += (size_t)gridDim.x * kThreads) {
+    const size_t bt = e / ((size_t)n * nv);  // block * nt + t
+    const size_t q = e - bt * (size_t)n * nv;
+    const int r = (int)(q / nv), v = (int)(q - (size_t)r * nv);
+    const int p = pos[r];
+    out[e] = p >= 0 ? x[(bt * nsub + p) * nv + v] : 0.f;
+  }
+}
+
 enum Phase { kQueued, kData, kInitAdj, kIterF, kIterA, kDone, kCanceled };
+
+// A problem size the server solves on: the full grid (the server's op) or a lattice level.
+struct Level {
+  mdc_op* op = nullptr;     // operator of the level
+  int n = 0;                // traces
+  int* idx = nullptr;       // device [n]: trace -> full-grid trace (lattice levels only)
+  int* pos = nullptr;       // device [nx^2]: full-grid trace -> lattice position or -1
+};
+constexpr int kLevels = 3;  // full grid, lattice of d = 2, lattice of d = 4
+
+int level_of(int decim) { return decim == 4 ? 2 : (decim == 2 ? 1 : 0); }
 
 struct Request {
   uint64_t id;
   int nv, niter, decim;
+  int lv = 0;             // level it is solved on (0: full grid)
+  int n = 0;              // traces of its problem
   PointArgs pts;
   float* x_out;
   double* hist;
@@ -109,19 +147,23 @@ struct Request {
   int it = 0;             // completed LSQR iterations
   int c0 = 0;             // first spectral column in the current step
   bool cancel = false;
+  bool deferred = false;  // waited for an adjoint step before admission (lockstep phases)
   bool finished = false;  // left the server (done or cancelled); set under the lock
   std::chrono::steady_clock::time_point arrival, finish;
 };
 
 // Partial-sum slots of one request's fused recurrences (two inverse segments per apply).
-int parts_for(const mdc_desc& d, int nv) { return 2 * irfft_blocks(d.nt, d.ns, nv); }
+int parts_for(int nt, int n, int nv) { return 2 * irfft_blocks(nt, n, nv); }
 
-size_t slot_bytes_for(const mdc_desc& d, int nv) {
-  const size_t vec = 2ull * d.nt * d.ns * nv * 4;  // two Marchenko blocks
-  size_t b = 2 * align_up((size_t)d.ns * nv * 4, 256);  // onset, keep
+// Arena bytes of a request on n traces: onsets, keep mask, scalars, partial sums, the Krylov
+// vectors u, v, w (recurrences fused into the applies) and, on a lattice level, its own
+// solution x (scattered onto the caller's full-grid output at the end).
+size_t slot_bytes_for(int nt, int n, int nv, bool lattice) {
+  const size_t vec = 2ull * nt * n * nv * 4;  // two Marchenko blocks
+  size_t b = 2 * align_up((size_t)n * nv * 4, 256);
   b += lsqr_scalars_bytes();
-  b += align_up((size_t)parts_for(d, nv) * sizeof(double), 256);  // partial sums
-  b += 3 * align_up(vec, 256);                        // u, v, w (recurrences fused into the applies)
+  b += align_up((size_t)parts_for(nt, n, nv) * sizeof(double), 256);
+  b += (lattice ? 4 : 3) * align_up(vec, 256);
   return b;
 }
 
@@ -131,6 +173,11 @@ class Arena {
   void reset(size_t size) {
     free_.clear();
     if (size) free_[0] = size;
+  }
+  bool fits(size_t bytes) const {
+    for (const auto& kv : free_)
+      if (kv.second >= bytes) return true;
+    return false;
   }
   bool alloc(size_t bytes, size_t* off) {
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -174,7 +221,9 @@ struct mdc_server {
   serve_geometry g{};
   char* arena_base = nullptr;
   size_t arena_bytes = 0;
+  size_t reserved = 0;                   // arena bytes held by the lattice levels
   Arena arena;
+  Level lv[kLevels];
   int device = 0;
   hipStream_t stream = nullptr;
   std::thread worker;
@@ -200,6 +249,13 @@ struct mdc_server {
   std::map<std::vector<uint64_t>, int> seen;
   bool graphs_ok = true;
   std::atomic<long> captured{0}, replayed{0};
+  // Lockstep phases: every admitted request applies the operator in the step's direction, and
+  // new requests (whose first application is a forward one) are admitted at forward steps only.
+  // A request that could have been admitted during an adjoint step waits for that step: the
+  // only delay a pass serving both directions at once would remove.
+  long deferred = 0;
+  double deferred_s = 0.0;
+  long request_steps = 0;               // sum over steps of the requests served
 };
 
 namespace {
@@ -208,12 +264,14 @@ int cols_for(const Request* r) { return r->phase == kData ? r->nv : 2 * r->nv; }
 
 bool wants_forward(const Request* r) { return r->phase == kData || r->phase == kIterF; }
 
-// Enqueue one fused step for the requests in `part` (all in the same direction).  Only
-// launches: the phase transitions are applied afterwards by advance().
-mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hipStream_t st) {
-  mdc_op* op = S->op;
+// Enqueue the launches of one level's requests in a step (all in the same direction): their
+// transforms into consecutive column ranges of the level's spectra, one product over all of
+// them, and their inverse transforms with the LSQR recurrences.  Only launches: the phase
+// transitions are applied afterwards by advance().
+mdc_status enqueue_level(mdc_server* S, const Level& L, std::vector<Request*>& part, bool fwd, hipStream_t st) {
+  mdc_op* op = L.op;
   const mdc_desc& d = op->d;
-  const int n = d.ns;
+  const int n = L.n;
   int N = 0;
   for (Request* r : part) {
     r->c0 = N;
@@ -258,7 +316,7 @@ mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hi
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_out, st)) != MDC_OK) return s;
       lsqr_after_fwd_fused(r->S, st);
     } else {  // alpha v = A^H u - beta v: [u0 - d keep R*^H Theta u1 ; u1 - d keep R^H Theta u0] - beta v
-      const int* km = r->decim > 1 ? r->keep : nullptr;
+      const int* km = (r->decim > 1 && r->lv == 0) ? r->keep : nullptr;  // lattice levels hold no other traces
       const Recur rec = r->phase == kInitAdj ? lsqr_recur_init(r->S) : lsqr_recur_adj(r->S);
       IfftSeg a{r->S.v + half, r->S.u + half, km, 0, r->c0, -dsc, 1.0f, lsqr_uinv(r->S)};
       IfftSeg b{r->S.v, r->S.u, km, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_uinv(r->S)};
@@ -271,6 +329,20 @@ mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hi
     }
   }
   return check_launch("serve step");
+}
+
+// One step: the levels present run one after another on the serving stream (they share the
+// op's workspace).
+mdc_status enqueue_step(mdc_server* S, std::vector<Request*>& part, bool fwd, hipStream_t st) {
+  for (int l = 0; l < kLevels; ++l) {
+    std::vector<Request*> group;
+    for (Request* r : part)
+      if (r->lv == l) group.push_back(r);
+    if (group.empty()) continue;
+    const mdc_status s = enqueue_level(S, S->lv[l], group, fwd, st);
+    if (s != MDC_OK) return s;
+  }
+  return MDC_OK;
 }
 
 // Phase transitions of the requests of a step that has been enqueued.
@@ -341,32 +413,46 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
   return s;
 }
 
+size_t request_bytes(const mdc_server* S, const Request* r) {
+  return slot_bytes_for(S->op->d.nt, r->n, r->nv, r->lv != 0);
+}
+
 // Give a request its arena slot and generate its inputs (called with the lock held).
 bool admit(mdc_server* S, Request* r) {
   const mdc_desc& d = S->op->d;
   size_t off;
-  const size_t bytes = slot_bytes_for(d, r->nv);
+  const size_t bytes = request_bytes(S, r);
   if (!S->arena.alloc(bytes, &off)) return false;
   r->slot_off = off;
   r->slot_bytes = bytes;
   char* p = S->arena_base + off;
-  const size_t vec = 2ull * d.nt * d.ns * r->nv;
-  r->onset = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
-  r->keep = reinterpret_cast<int*>(p); p += align_up((size_t)d.ns * r->nv * 4, 256);
+  const int n = r->n;
+  const size_t vec = 2ull * d.nt * n * r->nv;
+  r->onset = reinterpret_cast<int*>(p); p += align_up((size_t)n * r->nv * 4, 256);
+  r->keep = reinterpret_cast<int*>(p); p += align_up((size_t)n * r->nv * 4, 256);
   r->S.sc = p; p += lsqr_scalars_bytes();
-  r->S.rpart = reinterpret_cast<double*>(p); p += align_up((size_t)parts_for(d, r->nv) * sizeof(double), 256);
-  r->S.nparts_fwd = r->S.nparts_adj = parts_for(d, r->nv);
+  r->S.rpart = reinterpret_cast<double*>(p); p += align_up((size_t)parts_for(d.nt, n, r->nv) * sizeof(double), 256);
+  r->S.nparts_fwd = r->S.nparts_adj = parts_for(d.nt, n, r->nv);
   r->S.u = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
   r->S.v = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
-  r->S.w = reinterpret_cast<float*>(p);
+  r->S.w = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
   r->S.t = r->S.t2 = nullptr;
-  r->S.x = r->x_out;
+  r->S.x = r->lv != 0 ? reinterpret_cast<float*>(p) : r->x_out;
   r->S.hist = r->hist;
   r->S.model = r->S.data = vec;
   hipLaunchKernelGGL(request_inputs, dim3(2048), dim3(kThreads), 0, S->stream, d.nt, S->g.nx, S->g.dx, S->g.dt,
-                     S->g.c, S->g.eps, S->g.fp, r->decim, r->nv, r->pts, r->onset, r->keep, r->S.w);
+                     S->g.c, S->g.eps, S->g.fp, r->decim, n, (const int*)S->lv[r->lv].idx, r->nv, r->pts, r->onset,
+                     r->keep, r->S.w);
   r->phase = kData;
   return true;
+}
+
+// A finished lattice-level request's solution onto the caller's full-grid output.
+void finish_output(mdc_server* S, const Request* r) {
+  if (r->lv == 0) return;
+  const Level& L = S->lv[r->lv];
+  hipLaunchKernelGGL(scatter_lattice, dim3(2048), dim3(kThreads), 0, S->stream, (const float*)r->S.x, r->x_out,
+                     (const int*)L.pos, S->op->d.nt, S->op->d.ns, L.n, r->nv);
 }
 
 void release(mdc_server* S, Request* r) {
@@ -378,7 +464,7 @@ void worker_main(mdc_server* S) {
   hipSetDevice(S->device);
   const int max_cols = S->op->d.max_cols;
   while (true) {
-    std::vector<Request*> part;
+    std::vector<Request*> part, deferred_now;
     bool fwd;
     {
       std::unique_lock<std::mutex> lk(S->mu);
@@ -399,9 +485,18 @@ void worker_main(mdc_server* S) {
       }
       if (S->active.empty()) S->forward_next = true;
       fwd = S->forward_next;
+      int cols = 0;
+      for (Request* r : S->active) cols += 2 * r->nv;
+      if (!fwd) {  // lockstep: queued requests that would fit now wait for this adjoint step
+        int c = cols;
+        for (Request* r : S->queue) {
+          if (r->cancel) continue;
+          if (c + 2 * r->nv > max_cols || !S->arena.fits(request_bytes(S, r))) break;
+          c += 2 * r->nv;
+          deferred_now.push_back(r);
+        }
+      }
       if (fwd) {  // admission (new requests start with the forward data step)
-        int cols = 0;
-        for (Request* r : S->active) cols += 2 * r->nv;
         while (!S->queue.empty()) {
           Request* r = S->queue.front();
           if (r->cancel) {
@@ -423,14 +518,24 @@ void worker_main(mdc_server* S) {
       if ((int)S->active.size() > S->max_active) S->max_active = (int)S->active.size();
       S->forward_next = !fwd;
       if (part.empty()) continue;
+      S->request_steps += (long)part.size();
     }
+    const auto step_start = std::chrono::steady_clock::now();
     mdc_status st = run_step(S, part, fwd);
+    if (st == MDC_OK)
+      for (Request* r : part)
+        if (r->phase == kDone) finish_output(S, r);
     // always wait for the step, also after a failed launch, before any slot can be reused
     const hipError_t se = hipStreamSynchronize(S->stream);
     if (st == MDC_OK && se != hipSuccess) st = fail(MDC_EDEVICE, "serve step failed: %s", hipGetErrorString(se));
     const auto now = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     S->steps += 1;
+    for (Request* r : deferred_now) {  // still queued (admission happens under this lock)
+      if (!r->deferred) S->deferred += 1;
+      r->deferred = true;
+      S->deferred_s += std::chrono::duration<double>(now - step_start).count();
+    }
     if (st != MDC_OK) {  // fail every running request; the server stays up for new ones
       S->error = st;
       for (Request* r : part) r->phase = kCanceled;
@@ -455,6 +560,45 @@ void worker_main(mdc_server* S) {
   }
 }
 
+// Full-grid traces of the lattice of decimation d (the Sub2 / Sub4 rule), in trace order.
+std::vector<int> lattice_traces(int nx, int d) {
+  std::vector<int> idx;
+  for (int r = 0; r < nx * nx; ++r) {
+    const int ix = r / nx, iy = r % nx;
+    const bool keep = d == 2 ? ((ix + iy) & 1) == 0 : (((ix - iy) % 4) + 4) % 4 == 0;
+    if (keep) idx.push_back(r);
+  }
+  return idx;
+}
+
+size_t level_bytes(const mdc_op* op, int nx, int d) {
+  const size_t nsub = lattice_traces(nx, d).size();
+  return align_up(nsub * 4, 256) + align_up((size_t)nx * nx * 4, 256) + sub_op_resident_bytes(op, (int)nsub);
+}
+
+// Carve a lattice level out of the arena: index tables and the gathered kernel.
+mdc_status make_level(mdc_server* S, int d) {
+  const int nx = S->g.nx, n = nx * nx;
+  const std::vector<int> idx = lattice_traces(nx, d);
+  std::vector<int> pos(n, -1);
+  for (size_t i = 0; i < idx.size(); ++i) pos[idx[i]] = (int)i;
+  const size_t bytes = level_bytes(S->op, nx, d);
+  size_t off;
+  if (!S->arena.alloc(bytes, &off))
+    return fail(MDC_ENOMEM, "lattice level d=%d needs %zu bytes of the arena", d, bytes);
+  S->reserved += bytes;
+  Level& L = S->lv[level_of(d)];
+  char* p = S->arena_base + off;
+  L.n = (int)idx.size();
+  L.idx = reinterpret_cast<int*>(p); p += align_up(idx.size() * 4, 256);
+  L.pos = reinterpret_cast<int*>(p); p += align_up((size_t)n * 4, 256);
+  if (hipMemcpyAsync(L.idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+      hipMemcpyAsync(L.pos, pos.data(), (size_t)n * 4, hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+      hipStreamSynchronize(S->stream) != hipSuccess)  // the host tables go out of scope
+    return fail(MDC_EDEVICE, "uploading the lattice tables failed");
+  return sub_op_create(S->op, L.idx, L.n, p, S->stream, &L.op);
+}
+
 }  // namespace
 
 extern "C" {
@@ -462,7 +606,16 @@ extern "C" {
 mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes) {
   if (!op || !bytes) return fail(MDC_EINVAL, "NULL argument");
   if (nv < 1 || nv > kMaxPoints) return fail(MDC_EINVAL, "nv=%d outside [1, %d]", nv, kMaxPoints);
-  *bytes = slot_bytes_for(op->d, nv);
+  *bytes = slot_bytes_for(op->d.nt, op->d.ns, nv, false);
+  return MDC_OK;
+}
+
+mdc_status serve_level_bytes(const mdc_op* op, int decim, size_t* bytes) {
+  if (!op || !bytes) return fail(MDC_EINVAL, "NULL argument");
+  if (decim != 2 && decim != 4) return fail(MDC_EINVAL, "decimation must be 2 or 4");
+  const int nx = (int)std::lround(std::sqrt((double)op->d.ns));
+  if (nx * nx != op->d.ns || op->d.ns != op->d.nr) return fail(MDC_EINVAL, "not a square grid operator");
+  *bytes = level_bytes(op, nx, decim);
   return MDC_OK;
 }
 
@@ -473,6 +626,7 @@ mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t
   if (!(g->dt > 0) || !(g->dx > 0) || !(g->c > 0) || g->eps < 0) return fail(MDC_EINVAL, "bad geometry");
   if (!arena || !aligned(arena, 256)) return fail(MDC_EINVAL, "arena must be non-NULL and 256-byte aligned");
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
+  if (g->sublattice & ~6) return fail(MDC_EINVAL, "sublattice=%d: a combination of 2 and 4", g->sublattice);
   mdc_server* S = new (std::nothrow) mdc_server();
   if (!S) return fail(MDC_ENOMEM, "host allocation failed");
   S->op = op;
@@ -480,9 +634,30 @@ mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t
   S->arena_base = static_cast<char*>(arena);
   S->arena_bytes = arena_bytes / 256 * 256;
   S->arena.reset(S->arena_bytes);
+  S->lv[0].op = op;
+  S->lv[0].n = op->d.ns;
   if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
     delete S;
     return fail(MDC_EDEVICE, "creating the serving stream failed");
+  }
+  for (int dd : {2, 4}) {
+    if (!(g->sublattice & dd)) continue;
+    const mdc_status ls = make_level(S, dd);
+    if (ls != MDC_OK) {
+      hipStreamSynchronize(S->stream);
+      for (auto& L : S->lv)
+        if (L.op && L.op != op) mdc_destroy(L.op);
+      hipStreamDestroy(S->stream);
+      delete S;
+      return ls;
+    }
+  }
+  if (hipStreamSynchronize(S->stream) != hipSuccess) {
+    for (auto& L : S->lv)
+      if (L.op && L.op != op) mdc_destroy(L.op);
+    hipStreamDestroy(S->stream);
+    delete S;
+    return fail(MDC_EDEVICE, "preparing the lattice levels failed");
   }
   S->worker = std::thread(worker_main, S);
   *out = S;
@@ -498,13 +673,19 @@ mdc_status serve_submit(mdc_server* S, const serve_req* q, uint64_t* id) {
   if (!q->x_out || !aligned(q->x_out, 16)) return fail(MDC_EINVAL, "x_out must be non-NULL and 16-byte aligned");
   if (q->hist && !aligned(q->hist, 8)) return fail(MDC_EINVAL, "hist must be 8-byte aligned");
   if (2 * q->nv > S->op->d.max_cols) return fail(MDC_ENOMEM, "2*nv=%d exceeds the column budget %d", 2 * q->nv, S->op->d.max_cols);
-  if (slot_bytes_for(S->op->d, q->nv) > S->arena_bytes)
-    return fail(MDC_ENOMEM, "request needs %zu bytes, the arena has %zu", slot_bytes_for(S->op->d, q->nv), S->arena_bytes);
   Request* r = new (std::nothrow) Request();
   if (!r) return fail(MDC_ENOMEM, "host allocation failed");
   r->nv = q->nv;
   r->niter = q->niter;
   r->decim = q->decim;
+  r->lv = S->lv[level_of(q->decim)].op ? level_of(q->decim) : 0;
+  r->n = S->lv[r->lv].n;
+  const size_t need = request_bytes(S, r);
+  if (need > S->arena_bytes - S->reserved) {
+    delete r;
+    return fail(MDC_ENOMEM, "request needs %zu bytes, the arena has %zu free of levels", need,
+                S->arena_bytes - S->reserved);
+  }
   for (int v = 0; v < q->nv; ++v) {
     r->pts.vx[v] = q->vx[v];
     r->pts.vy[v] = q->vy[v];
@@ -538,14 +719,19 @@ mdc_status serve_poll(mdc_server* S, uint64_t id, int* done, double* latency_s) 
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->all.find(id);
   if (it == S->all.end()) return fail(MDC_EINVAL, "unknown request id %llu", (unsigned long long)id);
-  const Request* r = it->second;
+  Request* r = it->second;
   if (!r->finished) {
     *done = 0;
     return MDC_ENOTREADY;
   }
-  if (r->phase == kDone) {
+  // a finished request is reported once and then released
+  const bool ok = r->phase == kDone;
+  const double lat = std::chrono::duration<double>(r->finish - r->arrival).count();
+  S->all.erase(it);
+  delete r;
+  if (ok) {
     *done = 1;
-    if (latency_s) *latency_s = std::chrono::duration<double>(r->finish - r->arrival).count();
+    if (latency_s) *latency_s = lat;
     return MDC_OK;
   }
   *done = -1;
@@ -595,6 +781,15 @@ mdc_status serve_stats(mdc_server* S, int skip, double* solves_per_s, double* p5
   return MDC_OK;
 }
 
+mdc_status serve_phase_stats(mdc_server* S, long* request_steps, long* deferred, double* deferred_s) {
+  if (!S) return fail(MDC_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (request_steps) *request_steps = S->request_steps;
+  if (deferred) *deferred = S->deferred;
+  if (deferred_s) *deferred_s = S->deferred_s;
+  return MDC_OK;
+}
+
 mdc_status serve_graph_stats(mdc_server* S, long* captured, long* replayed) {
   if (!S) return fail(MDC_EINVAL, "NULL server");
   if (captured) *captured = S->captured.load();
@@ -613,6 +808,8 @@ mdc_status serve_destroy(mdc_server* S) {
   hipStreamSynchronize(S->stream);
   drop_graphs(S);
   hipStreamDestroy(S->stream);
+  for (auto& L : S->lv)
+    if (L.op && L.op != S->op) mdc_destroy(L.op);
   for (auto& kv : S->all) delete kv.second;
   delete S;
   return MDC_OK;

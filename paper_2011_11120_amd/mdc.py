@@ -49,7 +49,7 @@ class lsqr_desc(C.Structure):
 
 class serve_geometry(C.Structure):
     _fields_ = [("nx", C.c_int), ("dx", C.c_double), ("dt", C.c_double), ("c", C.c_double),
-                ("eps", C.c_int), ("fp", C.c_double)]
+                ("eps", C.c_int), ("fp", C.c_double), ("sublattice", C.c_int)]
 
 
 class serve_req(C.Structure):
@@ -89,6 +89,8 @@ def _load():
         "mch_neumann_query": (st, [vp, i, C.POINTER(C.c_size_t)]),
         "mch_neumann": (st, [vp, vp, i, vp, vp, i, vp, C.c_size_t, vp]),
         "serve_request_bytes": (st, [vp, i, C.POINTER(C.c_size_t)]),
+        "serve_level_bytes": (st, [vp, i, C.POINTER(C.c_size_t)]),
+        "serve_phase_stats": (st, [vp, C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_double)]),
         "serve_create": (st, [vp, C.POINTER(serve_geometry), vp, C.c_size_t, C.POINTER(vp)]),
         "serve_submit": (st, [vp, C.POINTER(serve_req), C.POINTER(C.c_uint64)]),
         "serve_poll": (st, [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -112,8 +114,8 @@ EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", 
            "mdc_profile", "mdc_profile_read", "mdc_destroy", "mdc_autotune", "mdc_tune_table",
            "lsqr_query_sizes", "lsqr_solve", "cgls_solve", "mdc_set_kernel_time", "mch_greens",
            "mch_neumann_query", "mch_neumann",
-           "serve_request_bytes", "serve_create", "serve_submit", "serve_poll", "serve_cancel", "serve_drain",
-           "serve_stats", "serve_graph_stats", "serve_destroy")
+           "serve_request_bytes", "serve_level_bytes", "serve_create", "serve_submit", "serve_poll",
+           "serve_cancel", "serve_drain", "serve_stats", "serve_phase_stats", "serve_graph_stats", "serve_destroy")
 
 
 def _check(status: int):
@@ -265,6 +267,18 @@ def serve_request_bytes(h, nv) -> int:
     return n.value
 
 
+def serve_level_bytes(h, decim) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.serve_level_bytes(h, int(decim), C.byref(n)))
+    return n.value
+
+
+def serve_phase_stats(srv):
+    rs, dfr, dfs = C.c_long(), C.c_long(), C.c_double()
+    _check(_lib.serve_phase_stats(srv, C.byref(rs), C.byref(dfr), C.byref(dfs)))
+    return {"request_steps": rs.value, "deferred": dfr.value, "deferred_s": dfs.value}
+
+
 def serve_create(h, geom: serve_geometry, arena):
     srv = C.c_void_p()
     _check(_lib.serve_create(h, C.byref(geom), _ptr(arena), C.c_size_t(arena.numel() * arena.element_size()),
@@ -317,12 +331,19 @@ def serve_destroy(srv):
 class Server:
     """Owns the arena (PyTorch) and the library server over an MdcOp."""
 
-    def __init__(self, op, nx, arena_bytes=None, dx=20.0, dt=0.004, c=2000.0, eps=6, fp=20.0, arena=None):
+    def __init__(self, op, nx, arena_bytes=None, dx=20.0, dt=0.004, c=2000.0, eps=6, fp=20.0, arena=None,
+                 sublattice=0):
+        """sublattice: decimation levels (2, 4 or 6 for both) solved on their own lattice with a
+        kernel gathered into the arena; arena_bytes counts the request slots only, the levels'
+        bytes (serve_level_bytes) are added to it."""
         self.op = op
         self.nt, self.n = op.nt, op.ns
-        self.arena = arena if arena is not None else torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        if arena is None:
+            extra = sum(serve_level_bytes(op.handle, d) for d in (2, 4) if sublattice & d)
+            arena = torch.empty(int(arena_bytes) + extra, dtype=torch.uint8, device="cuda")
+        self.arena = arena
         torch.cuda.synchronize()
-        self.handle = serve_create(op.handle, serve_geometry(nx, dx, dt, c, eps, fp), self.arena)
+        self.handle = serve_create(op.handle, serve_geometry(nx, dx, dt, c, eps, fp, sublattice), self.arena)
         self._keep = {}
 
     def submit(self, vx, vy, vz, niter, decim=1, x_out=None, hist=True):
@@ -356,6 +377,9 @@ class Server:
 
     def graph_stats(self):
         return serve_graph_stats(self.handle)
+
+    def phase_stats(self):
+        return serve_phase_stats(self.handle)
 
     def close(self):
         if self.handle is not None:

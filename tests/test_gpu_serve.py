@@ -1,4 +1,10 @@
-"""Serving loop: per-request parity with the oracle, alone vs mix, admission, errors, cancel."""
+"""Serving loop: per-request parity with the oracle, alone vs mix, admission, errors, cancel.
+
+Every storage format is served: FP32 to 1e-5 against the FP64 oracle, the 16-bit formats to
+the 1e-3 model-error budget (solution and phibar history).  Decimated requests run either on
+the full grid with zero traces (sublattice 0) or on their own lattice with a gathered kernel
+(sublattice 2|4); both must give the oracle's solution of the decimated problem.
+"""
 import numpy as np
 import pytest
 import torch
@@ -31,12 +37,16 @@ def spec_for(d):
     return workloads.marchenko_spec(nx=NX, nt=NT, nfmax=NF, d=d, kappa_value=kap), kap
 
 
-@pytest.fixture(scope="module")
-def served(mdcmod):
+TOL = {"fp32": 1e-5, "fp16s": 1e-3, "bf16x2": 1e-3, "fp16": 1e-3}
+
+
+@pytest.fixture(scope="module", params=["fp32", "fp16s", "bf16x2", "fp16"])
+def served(mdcmod, request):
     spec, kap = spec_for(1)
-    op = mdcmod.MdcOp(NT, NF, NX * NX, NX * NX, max_cols=64)
+    op = mdcmod.MdcOp(NT, NF, NX * NX, NX * NX, max_cols=64, prec=request.param)
     op.synth_kernel(spec)
-    return op, kap
+    yield op, kap, request.param
+    op.close()
 
 
 def points(nv, seed):
@@ -57,9 +67,11 @@ def oracle_solution(kap, decim, vx, vy, vz, niter):
 REQS = [(1, 4, 1), (3, 6, 1), (2, 5, 2), (5, 3, 4), (1, 7, 2), (4, 2, 1)]
 
 
-def test_requests_in_a_mix_match_oracle(mdcmod, served):
-    op, kap = served
-    srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+@pytest.mark.parametrize("sublattice", [0, 6])
+def test_requests_in_a_mix_match_oracle(mdcmod, served, sublattice):
+    op, kap, prec = served
+    tol = TOL[prec]
+    srv = mdcmod.Server(op, NX, arena_bytes=1 << 30, sublattice=sublattice)
     ids = []
     for k, (nv, niter, decim) in enumerate(REQS):
         vx, vy, vz = points(nv, k)
@@ -73,34 +85,60 @@ def test_requests_in_a_mix_match_oracle(mdcmod, served):
         x, h = srv.result(rid)
         xg = x.cpu().numpy().astype(np.float64)
         idx, xr, hr = oracle_solution(kap, decim, vx, vy, vz, niter)
-        print(f"request nv={nv} niter={niter} d={decim}: err {rel2(xg[:, :, idx], xr):.2e}", flush=True)
-        assert rel2(xg[:, :, idx], xr) < 1e-5
+        eh = np.max(np.abs(h.cpu().numpy() - hr) / hr[0])
+        print(f"{prec} sublattice={sublattice} request nv={nv} niter={niter} d={decim}: "
+              f"err {rel2(xg[:, :, idx], xr):.2e} history {eh:.2e}", flush=True)
+        assert rel2(xg[:, :, idx], xr) < tol
         off = np.setdiff1d(np.arange(NX * NX), idx)
         assert np.all(xg[:, :, off] == 0)
-        assert np.max(np.abs(h.cpu().numpy() - hr) / hr[0]) < 1e-5
+        assert eh < tol
+        with pytest.raises(mdcmod.MdcError) as ei:  # reported once, then released
+            srv.poll(rid)
+        assert ei.value.status == mdcmod.MDC_EINVAL
+    ps = srv.phase_stats()
+    assert ps["request_steps"] >= sum(2 * it + 2 for _, it, _ in REQS) and ps["deferred"] >= 0
     srv.close()
 
 
-def test_alone_equals_mix(mdcmod, served):
-    op, kap = served
+def test_sublattice_equals_full_grid(mdcmod, served):
+    """A decimated request gives the same solution on its gathered lattice kernel as on the full grid
+    with zero traces (the two encodings of the decimated problem)."""
+    op, kap, prec = served
+    tol = 1e-5 if prec == "fp32" else 1e-3
+    out = {}
+    for sub in (0, 6):
+        srv = mdcmod.Server(op, NX, arena_bytes=1 << 28, sublattice=sub)
+        ids = [srv.submit(*points(3, 123), 6, d) for d in (2, 4)]
+        srv.drain()
+        out[sub] = [srv.result(i)[0].cpu().numpy() for i in ids]
+        srv.close()
+    for a, b in zip(out[0], out[6]):
+        assert rel2(b, a) < tol
+
+
+@pytest.mark.parametrize("sublattice", [0, 6])
+def test_alone_equals_mix(mdcmod, served, sublattice):
+    op, kap, prec = served
     vx, vy, vz = points(3, 99)
-    alone = mdcmod.Server(op, NX, arena_bytes=1 << 28)
+    alone = mdcmod.Server(op, NX, arena_bytes=1 << 28, sublattice=sublattice)
     ra = alone.submit(vx, vy, vz, 5, 2)
     alone.drain()
     xa = alone.result(ra)[0].clone()
     alone.close()
-    mix = mdcmod.Server(op, NX, arena_bytes=1 << 30)
-    others = [mix.submit(*points(nv, 50 + k), 6, 1) for k, nv in enumerate((8, 16, 4))]
+    mix = mdcmod.Server(op, NX, arena_bytes=1 << 30, sublattice=sublattice)
+    others = [mix.submit(*points(nv, 50 + k), 6, d) for k, (nv, d) in enumerate(((8, 1), (16, 2), (4, 2)))]
     rm = mix.submit(vx, vy, vz, 5, 2)
     mix.drain()
     xm = mix.result(rm)[0]
     assert mix.stats()["max_active"] >= 2
-    assert rel2(xm.cpu().numpy(), xa.cpu().numpy()) < 1e-5
+    err = rel2(xm.cpu().numpy(), xa.cpu().numpy())
+    print(f"{prec} sublattice={sublattice}: alone vs mix {err:.2e}", flush=True)
+    assert err < (1e-5 if prec == "fp32" else 1e-3)
     mix.close()
 
 
 def test_admission_by_footprint(mdcmod, served):
-    op, kap = served
+    op, kap, prec = served
     per = mdcmod.serve_request_bytes(op.handle, 4)
     srv = mdcmod.Server(op, NX, arena_bytes=2 * per + per // 2)
     ids = [srv.submit(*points(4, k), 3, 1) for k in range(5)]
@@ -131,7 +169,7 @@ def test_column_budget_rejects_wide_requests(mdcmod):
 
 
 def test_cancel_leaves_others_intact(mdcmod, served):
-    op, kap = served
+    op, kap, prec = served
     srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
     keep_pts = points(2, 7)
     long_id = srv.submit(*points(6, 3), 400, 1)
@@ -142,16 +180,17 @@ def test_cancel_leaves_others_intact(mdcmod, served):
     assert srv.poll(rid)[0] == 1
     x = srv.result(rid)[0].cpu().numpy().astype(np.float64)
     idx, xr, _ = oracle_solution(kap, 1, *keep_pts, 4)
-    assert rel2(x[:, :, idx], xr) < 1e-5
+    assert rel2(x[:, :, idx], xr) < TOL[prec]
     srv.close()
 
 
 def test_graph_replayed_steps_match_eager_steps(mdcmod, served, monkeypatch):
     """Steps replayed from captured hipGraphs give the results of eagerly launched steps."""
-    op, kap = served
+    op, kap, prec = served
+    tol = TOL[prec]
 
     def run():
-        srv = mdcmod.Server(op, NX, arena_bytes=1 << 30)
+        srv = mdcmod.Server(op, NX, arena_bytes=1 << 30, sublattice=6)
         # iteration counts close together, so each composition of active requests lasts
         # several steps (a composition is captured on its second step, replayed after)
         mix = [(1, 9, 1), (3, 9, 1), (2, 10, 2), (5, 9, 4), (1, 10, 2), (4, 9, 1)]
@@ -172,6 +211,6 @@ def test_graph_replayed_steps_match_eager_steps(mdcmod, served, monkeypatch):
     assert gs1["captured"] > 0 and gs1["replayed"] > gs1["captured"]
     for (nv, niter, decim, vx, vy, vz), (xe, he), (xg, hg) in zip(reqs, eager, graphed):
         # step compositions may differ between runs (admission timing), hence the tolerance
-        assert rel2(xg.cpu().numpy(), xe.cpu().numpy()) < 1e-5
+        assert rel2(xg.cpu().numpy(), xe.cpu().numpy()) < tol
         idx, xr, hr = oracle_solution(kap, decim, vx, vy, vz, niter)
-        assert rel2(xg.cpu().numpy().astype(np.float64)[:, :, idx], xr) < 1e-5
+        assert rel2(xg.cpu().numpy().astype(np.float64)[:, :, idx], xr) < tol
