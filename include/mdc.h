@@ -169,6 +169,19 @@ mdc_status mdc_forward(mdc_op* op, const float* x, float* y, int nv, void* strea
 /* Adjoint (Eq.3 right): x[t][r][v] from y[t][s][v]. */
 mdc_status mdc_adjoint(mdc_op* op, const float* y, float* x, int nv, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mdc_forward (adjoint = 0) or mdc_adjoint
+ * (adjoint = 1) with the apply's spectra in a static device array of the library instead of the
+ * op's workspace.  The array holds 64 MiB (MDC_NOALLOC_SCRATCH_BYTES) on every GPU the library
+ * runs on, until the process ends; an apply whose spectra need more (nfmax * (ns + nr) * nv * 8
+ * bytes, plus the 16-bit split buffers) returns MDC_ENOMEM.  nv is not bounded by the op's
+ * max_cols.  The call allocates nothing; the array's device address is looked up once per device
+ * (at mdc_create, else at the first call).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (different streams, threads or ops) race and must be serialised by the
+ * caller.  The op's own workspace is not touched, so mdc_forward / mdc_adjoint may overlap it. */
+#define MDC_NOALLOC_SCRATCH_BYTES (64u << 20)
+mdc_status mdc_apply_noalloc(mdc_op* op, int adjoint, const float* in, float* out, int nv, void* stream);
+
 /* Marchenko operator of Eq.5 on a square op (ns == nr == n) with 2*nv <= max_cols:
  *   forward  (o0, o1) = (in0 - Theta R in1,  in1 - Theta R* in0)
  *   adjoint  (o0, o1) = (in0 - R*^H Theta in1,  in1 - R^H Theta in0)

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -57,15 +58,15 @@ enum Family { kFamGemv = 0, kFamGemm64 = 1, kFamGemm32 = 2 };
 // Default crossover without tuning: streaming kernels up to 8 columns.
 static constexpr int kGemvMaxCols = 8;
 
+// d: the op's descriptor, or a copy whose max_cols sizes the split-spectra buffer bsplit.
 static mdc_status run_family(const mdc_op* op, int fam, int adjoint, const float2* in, float2* out, int ncols,
-                             hipStream_t st) {
-  const mdc_desc& d = op->d;
+                             hipStream_t st, const mdc_desc& d, unsigned int* bsplit) {
   const int ldk = kernel_ld(d.nr);
   if (fam == kFamGemv) return gemv_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, st);
   if (d.prec == MDC_FP32)
     return gemm_launch(d, static_cast<const float2*>(op->kstore), ldk, adjoint, in, out, ncols, st,
                        fam == kFamGemm32 ? 32 : 64);
-  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, op->bsplit, st);
+  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, bsplit, st);
 }
 
 int forced_family(const mdc_op* op) {
@@ -90,7 +91,7 @@ int choose_family(const mdc_op* op, int adjoint, int ncols) {
 }
 
 mdc_status product_launch(const mdc_op* op, int adjoint, const float2* in, float2* out, int ncols, hipStream_t st) {
-  return run_family(op, choose_family(op, adjoint, ncols), adjoint, in, out, ncols, st);
+  return run_family(op, choose_family(op, adjoint, ncols), adjoint, in, out, ncols, st, op->d, op->bsplit);
 }
 
 // Time one family at one width on the op's own kernel (ms per launch, best of 3).
@@ -101,10 +102,10 @@ float time_family(mdc_op* op, int fam, int adjoint, int ncols, hipStream_t st) {
   hipEventCreate(&a);
   hipEventCreate(&b);
   float best = 3.0e38f;
-  if (run_family(op, fam, adjoint, in, out, ncols, st) == MDC_OK) {  // warm-up
+  if (run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit) == MDC_OK) {  // warm-up
     for (int rep = 0; rep < 3; ++rep) {
       hipEventRecord(a, st);
-      run_family(op, fam, adjoint, in, out, ncols, st);
+      run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit);
       hipEventRecord(b, st);
       hipEventSynchronize(b);
       float ms = 0.f;
@@ -197,20 +198,32 @@ mdc_status check_vec(const void* p, const char* name) {
   return MDC_OK;
 }
 
+// Spectra buffers of one apply: the op's workspace, or another buffer carved the same way for a
+// descriptor copy d whose max_cols is the apply's width.
+struct Spectra {
+  float2 *R, *S;
+  unsigned int* split;
+  mdc_desc d;
+};
+
 // pre: optional window [nr][nv] on the model side (a time-domain preconditioner P, so the
-// operator is C P, adjoint P C^H), or nullptr.
+// operator is C P, adjoint P C^H), or nullptr.  ws: spectra buffers replacing the op's workspace.
 mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st,
-                       const int* pre = nullptr, const double* in_scale = nullptr, const Recur* rec = nullptr) {
+                       const int* pre = nullptr, const double* in_scale = nullptr, const Recur* rec = nullptr,
+                       const Spectra* ws = nullptr) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
-  if (nv < 1 || nv > d.max_cols) return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, d.max_cols);
+  if (nv < 1 || nv > (ws ? ws->d.max_cols : d.max_cols))
+    return fail(MDC_EINVAL, "nv=%d outside [1, max_cols=%d]", nv, ws ? ws->d.max_cols : d.max_cols);
   mdc_status s;
   if ((s = check_vec(in, "input")) != MDC_OK) return s;
   if ((s = check_vec(out, "output")) != MDC_OK) return s;
   const int nin = adjoint ? d.ns : d.nr;
   const int nout = adjoint ? d.nr : d.ns;
-  float2* spec_in = adjoint ? op->specS : op->specR;
-  float2* spec_out = adjoint ? op->specR : op->specS;
+  float2* sR = ws ? ws->R : op->specR;
+  float2* sS = ws ? ws->S : op->specS;
+  float2* spec_in = adjoint ? sS : sR;
+  float2* spec_out = adjoint ? sR : sS;
   {
     Stage t(op, 0, st);
     FftSeg seg{in, adjoint ? nullptr : pre, 0, 0, in_scale};
@@ -218,7 +231,9 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   }
   {
     Stage t(op, adjoint ? 2 : 1, st);
-    if ((s = product_launch(op, adjoint, spec_in, spec_out, nv, st)) != MDC_OK) return s;
+    s = ws ? run_family(op, choose_family(op, adjoint, nv), adjoint, spec_in, spec_out, nv, st, ws->d, ws->split)
+           : product_launch(op, adjoint, spec_in, spec_out, nv, st);
+    if (s != MDC_OK) return s;
   }
   {
     Stage t(op, 3, st);
@@ -522,6 +537,36 @@ mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint,
 }
 }  // namespace mdc
 
+namespace {
+
+// Spectra of mdc_apply_noalloc: a fixed device array instead of caller memory.  In host code the
+// array's name is not a device address; the address comes from hipGetSymbolAddress, once per
+// device, with that device current.  Every launch writes all of the scratch it later reads
+// (transforms, split pass, per-frequency maxima), so nothing needs clearing between calls.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+mdc_status scratch_on_device(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(MDC_EDEVICE, "no usable current device for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MDC_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MDC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mdc_last_error(void) { return g_err; }
@@ -567,6 +612,10 @@ mdc_status mdc_create(const mdc_desc* desc, void* resident, void* workspace, voi
     delete op;
     return fail(MDC_EDEVICE, "uploading FFT table failed");
   }
+  // set-up of the static scratch of mdc_apply_noalloc on this device (its address is looked up
+  // here, outside any capture; a failure is reported by mdc_apply_noalloc itself)
+  char* sp = nullptr;
+  (void)scratch_on_device(&sp);
   *out = op;
   return MDC_OK;
 }
@@ -706,6 +755,26 @@ mdc_status mdc_forward(mdc_op* op, const float* x, float* y, int nv, void* strea
 mdc_status mdc_adjoint(mdc_op* op, const float* y, float* x, int nv, void* stream) {
   if (!op) return fail(MDC_EINVAL, "op is NULL");
   return apply_plain(op, y, x, nv, 1, static_cast<hipStream_t>(stream));
+}
+
+mdc_status mdc_apply_noalloc(mdc_op* op, int adjoint, const float* in, float* out, int nv, void* stream) {
+  if (!op) return fail(MDC_EINVAL, "op is NULL");
+  if (adjoint != 0 && adjoint != 1) return fail(MDC_EINVAL, "adjoint must be 0 or 1");
+  if (nv < 1) return fail(MDC_EINVAL, "nv=%d must be positive", nv);
+  Spectra ws{};
+  ws.d = op->d;
+  ws.d.max_cols = nv;  // the buffers are carved for this width only
+  const Layout L = layout_of(ws.d);
+  if (L.work > kScratchBytes)
+    return fail(MDC_ENOMEM, "an apply of %d columns needs %zu bytes of spectra; the static scratch holds %zu", nv,
+                L.work, kScratchBytes);
+  char* base = nullptr;
+  mdc_status s = scratch_on_device(&base);
+  if (s != MDC_OK) return s;
+  ws.R = reinterpret_cast<float2*>(base + L.specR);
+  ws.S = reinterpret_cast<float2*>(base + L.specS);
+  ws.split = op->d.prec != MDC_FP32 ? reinterpret_cast<unsigned int*>(base + L.bsplit) : nullptr;
+  return apply_plain(op, in, out, nv, adjoint, static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr, &ws);
 }
 
 mdc_status mch_forward(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,

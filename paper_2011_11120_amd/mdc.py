@@ -20,6 +20,7 @@ MDC_OK, MDC_EINVAL, MDC_ENOMEM, MDC_EDEVICE, MDC_EBUSY, MDC_ENOTREADY, MDC_ECANC
     0, -1, -2, -3, -4, -5, -6, -7
 MDC_FP32, MDC_FP16S, MDC_BF16, MDC_BF16X2, MDC_FP16 = 0, 1, 2, 3, 4
 MDC_OP_MDC, MDC_OP_MARCHENKO = 0, 1
+MDC_NOALLOC_SCRATCH_BYTES = 64 << 20  # static scratch of mdc_apply_noalloc (include/mdc.h)
 PREC = {"fp32": MDC_FP32, "fp16s": MDC_FP16S, "bf16": MDC_BF16, "bf16x2": MDC_BF16X2, "fp16": MDC_FP16}
 
 
@@ -72,6 +73,7 @@ def _load():
         "mdc_kernel_element": (st, [vp, i, i, i, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mdc_forward": (st, [vp, vp, vp, i, vp]),
         "mdc_adjoint": (st, [vp, vp, vp, i, vp]),
+        "mdc_apply_noalloc": (st, [vp, i, vp, vp, i, vp]),
         "mch_forward": (st, [vp, vp, i, vp, vp, vp, vp, vp]),
         "mch_adjoint": (st, [vp, vp, i, vp, vp, vp, vp, vp]),
         "mch_data": (st, [vp, vp, i, vp, vp, vp, vp]),
@@ -110,7 +112,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("mdc_last_error", "mdc_query_sizes", "mdc_create", "mdc_set_kernel", "mdc_synth_kernel",
-           "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mch_forward", "mch_adjoint", "mch_data",
+           "mdc_kernel_element", "mdc_forward", "mdc_adjoint", "mdc_apply_noalloc", "mch_forward", "mch_adjoint", "mch_data",
            "mdc_profile", "mdc_profile_read", "mdc_destroy", "mdc_autotune", "mdc_tune_table",
            "lsqr_query_sizes", "lsqr_solve", "cgls_solve", "mdc_set_kernel_time", "mch_greens",
            "mch_neumann_query", "mch_neumann",
@@ -175,6 +177,10 @@ def mdc_forward(h, x, y, nv, stream=None):
 
 def mdc_adjoint(h, y, x, nv, stream=None):
     _check(_lib.mdc_adjoint(h, _ptr(y), _ptr(x), int(nv), _stream(stream)))
+
+
+def mdc_apply_noalloc(h, adjoint, x, y, nv, stream=None):
+    _check(_lib.mdc_apply_noalloc(h, 1 if adjoint else 0, _ptr(x), _ptr(y), int(nv), _stream(stream)))
 
 
 def mch_forward(h, onset, nv, in0, in1, out0, out1, stream=None):
