@@ -149,10 +149,17 @@ def main():
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload; "
                          "c4: Marchenko LSQR solves (full, 2x, 4x decimated); c5: served stream of solves")
-    ap.add_argument("--requests", type=int, default=10, help="c5: requests per run")
-    ap.add_argument("--skip", type=int, default=2, help="c5: first completions left out of the latency stats")
+    ap.add_argument("--requests", type=int, default=64, help="c5: requests per run")
+    ap.add_argument("--skip", type=int, default=8, help="c5: first completions left out of the latency stats")
     ap.add_argument("--c5-precs", default="fp32,fp16s", help="c5: kernel formats to serve, in order")
     ap.add_argument("--c5-max-cols", type=int, default=384, help="c5: column budget (2 per focusing point)")
+    ap.add_argument("--c5-sublattice", type=int, default=6,
+                    help="c5: decimation levels solved on their own lattice (0, 2, 4 or 6)")
+    ap.add_argument("--c5-rate", type=float, default=None,
+                    help="c5: Poisson rate (solves/s) measured as 0.7 x the FP32 capacity in an earlier run")
+    ap.add_argument("--c5-light", type=float, default=0.0,
+                    help="c5: light-load Poisson stream at this fraction of the format's capacity (0: none)")
+    ap.add_argument("--c5-light-requests", type=int, default=24, help="c5: requests of the light-load stream")
     ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2", "fp16"], default="fp32",
                     help="kernel storage format for the c3/c4 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -442,7 +449,7 @@ def serve_run(srv, reqs, rate=None, cap=6, keep=()):
                 out[k] = lat
                 if k in keep:
                     kept[k] = srv.result(rid)[0].cpu()
-                srv._keep.pop(rid, None)
+                srv.release(rid)
                 print(f"  request {k}: nv={reqs[k]['nv']} it={reqs[k]['niter']} d={reqs[k]['decim']} "
                       f"latency {lat:.2f} s", file=sys.stderr, flush=True)
         time.sleep(0.002)
@@ -450,61 +457,82 @@ def serve_run(srv, reqs, rate=None, cap=6, keep=()):
     return out, kept
 
 
+def c5_leg(mdc, op, spec, reqs, arena_t, args, rate=None, keep=()):
+    """One served stream; every figure comes from the server's own statistics: solves/s = completions /
+    (last completion - first submission), p50/p99 over the completions after the first `skip`."""
+    srv = mdc.Server(op, spec.nx, dx=spec.dx, dt=spec.dt, arena=arena_t, sublattice=args.c5_sublattice)
+    lat, kept = serve_run(srv, reqs, rate=rate, keep=keep)
+    st, gs, ps = srv.stats(skip=args.skip), srv.graph_stats(), srv.phase_stats()
+    srv.close()
+    return {"requests": len(reqs), "solves_per_s": round(st["solves_per_s"], 4),
+            "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+            "latency_samples": st["completed"] - min(args.skip, st["completed"]),
+            "mean_latency_s": round(float(sum(lat.values()) / max(1, len(lat))), 3),
+            "max_active": st["max_active"], "steps": st["steps"],
+            "graph_steps": {"captured": gs["captured"], "replayed": gs["replayed"]},
+            "lockstep": {"request_steps": ps["request_steps"], "deferred_requests": ps["deferred"],
+                         "deferred_wait_s": round(ps["deferred_s"], 3)}}, kept
+
+
 def bench_c5(args):
-    """Served stream: 100 x 100 traces, nfmax=200, nt=1024; FP32 vs 16-bit kernel storage."""
+    """Served stream: 100 x 100 traces, nfmax=200, nt=1024; FP32 vs 16-bit kernel storage.
+
+    Per format: a closed loop (6 outstanding requests) gives the capacity; a Poisson stream at 0.7 x
+    the FP32 capacity (the same rate for every format), and for the 16-bit formats a second one at
+    0.7 x their own capacity; optionally a light-load stream (--c5-light, a fraction of the format's
+    capacity) on the first requests, where the lockstep statistics show what a pass serving both
+    directions at once could save."""
     import numpy as np
     import torch
     from paper_2011_11120_amd import mdc, workloads
     spec = workloads.marchenko_spec(nx=100, nt=1024, nfmax=200, kappa_value=workloads.kappa("c5"))
     reqs = c5_requests(args.requests)
     results, sols = {}, {}
-    rate = None
-    for prec in args.c5_precs.split(","):
+    rate32 = args.c5_rate
+    precs = args.c5_precs.split(",")
+    for prec in precs:
         op = mdc.MdcOp(spec.nt, spec.nfmax, spec.n, spec.n, max_cols=args.c5_max_cols, prec=prec)
         op.synth_kernel(spec)
         mdc.mdc_autotune(op.handle)
         torch.cuda.synchronize()
         free = torch.cuda.mem_get_info()[0]
-        out_bytes = 6 * 2 * spec.nt * spec.n * 64 * 4  # room for the outputs of 6 outstanding requests
-        arena = int(max(free - out_bytes - (6 << 30), 1 << 30))
+        outs = sorted((2 * spec.nt * spec.n * r["nv"] * 4 for r in reqs), reverse=True)
+        out_bytes = sum(outs[:6])  # outputs of the (at most) 6 outstanding requests
+        levels = sum(mdc.serve_level_bytes(op.handle, d) for d in (2, 4) if args.c5_sublattice & d)
+        arena = int(max(free - out_bytes - (4 << 30), levels + (1 << 30)))
         arena_t = torch.empty(arena, dtype=torch.uint8, device="cuda")
-        srv = mdc.Server(op, 100, dx=spec.dx, dt=spec.dt, arena=arena_t)
-        print(f"{prec}: kernel {op.resident.numel() / 1e9:.1f} GB, arena {arena / 1e9:.1f} GB", file=sys.stderr,
-              flush=True)
-        res = {}
-        for mode in ("closed", "poisson"):
-            if mode == "poisson" and rate is None:
-                continue
-            t0 = time.perf_counter()
-            lat, kept = serve_run(srv, reqs, rate=rate if mode == "poisson" else None, keep=(0, 1))
-            st = srv.stats(skip=0)
-            gs = srv.graph_stats()
-            srv.close()
-            srv = mdc.Server(op, 100, dx=spec.dx, dt=spec.dt, arena=arena_t)
-            l = np.array([lat[k] for k in sorted(lat)])[args.skip:]
-            res[mode] = {"solves_per_s": round(len(lat) / (time.perf_counter() - t0), 4),
-                         "p50_s": round(float(np.percentile(l, 50)), 3), "p99_s": round(float(np.percentile(l, 99)), 3),
-                         "max_active": st["max_active"], "steps": st["steps"],
-                         "graph_steps": {"captured": gs["captured"], "replayed": gs["replayed"]}}
-            if mode == "closed":
-                sols[prec] = kept
-                if rate is None:
-                    rate = 0.7 * res[mode]["solves_per_s"]
-                    res[mode]["poisson_rate_set_here"] = round(rate, 4)
-        srv.close()
-        results[prec] = {"kernel_GB": round(op.resident.numel() / 1e9, 1), "arena_GB": round(arena / 1e9, 1), **res}
+        print(f"{prec}: kernel {op.resident.numel() / 1e9:.1f} GB, arena {arena / 1e9:.1f} GB "
+              f"({levels / 1e9:.1f} GB lattice levels)", file=sys.stderr, flush=True)
+        res = {"kernel_GB": round(op.resident.numel() / 1e9, 1), "arena_GB": round(arena / 1e9, 1),
+               "lattice_levels_GB": round(levels / 1e9, 1)}
+        res["closed"], sols[prec] = c5_leg(mdc, op, spec, reqs, arena_t, args, keep=(0, 1))
+        cap = res["closed"]["solves_per_s"]
+        if prec == "fp32" and rate32 is None:
+            rate32 = 0.7 * cap
+        if rate32 is not None:
+            res["poisson_fp32_rate"], _ = c5_leg(mdc, op, spec, reqs, arena_t, args, rate=rate32)
+            res["poisson_fp32_rate"]["rate_per_s"] = round(rate32, 4)
+        if prec != "fp32":
+            res["poisson_own_rate"], _ = c5_leg(mdc, op, spec, reqs, arena_t, args, rate=0.7 * cap)
+            res["poisson_own_rate"]["rate_per_s"] = round(0.7 * cap, 4)
+        if args.c5_light > 0:
+            light = reqs[:args.c5_light_requests]
+            res["poisson_light"], _ = c5_leg(mdc, op, spec, light, arena_t, args, rate=args.c5_light * cap)
+            res["poisson_light"]["rate_per_s"] = round(args.c5_light * cap, 4)
+        results[prec] = res
         op.close()
-        del op, srv, arena_t
+        del op, arena_t
         torch.cuda.empty_cache()
     diff = {}
-    precs = args.c5_precs.split(",")
     for p in precs[1:]:
         diff[p] = {k: float(torch.linalg.vector_norm(sols[p][k] - sols[precs[0]][k]) /
                             torch.linalg.vector_norm(sols[precs[0]][k])) for k in sols[p]}
     print(json.dumps({"workload": "served Marchenko LSQR, 100x100 traces, nfmax=200, nt=1024, "
-                                  f"{len(reqs)} requests (nv 1-64, 10-60 it, d 1/2/4), first {args.skip} excluded",
+                                  f"{len(reqs)} requests (nv 1-64, 10-60 it, d 1/2/4), first {args.skip} "
+                                  "completions excluded from p50/p99",
+                      "sublattice": args.c5_sublattice, "column_budget": args.c5_max_cols,
                       "requests": [{k: r[k] for k in ("nv", "niter", "decim")} for r in reqs],
-                      "results": results, "poisson_rate_per_s": rate,
+                      "results": results, "poisson_rate_fp32_capacity_x0.7": rate32,
                       "solution_rel_diff_vs_" + precs[0]: diff}), flush=True)
 
 

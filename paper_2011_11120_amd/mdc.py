@@ -369,6 +369,10 @@ class Server:
     def result(self, rid):
         return self._keep[rid]
 
+    def release(self, rid):
+        """Drop this wrapper's reference to a finished request's output buffers."""
+        self._keep.pop(rid, None)
+
     def poll(self, rid):
         return serve_poll(self.handle, rid)
 
