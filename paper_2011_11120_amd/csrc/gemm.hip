@@ -14,11 +14,13 @@
 //                        (Y[s][v] = e + i f).
 //
 // One MFMA k-step of depth 4 consumes two complex columns of the kernel.  The
-// B fragments are formed from the complex spectra held in LDS at read time.
-// Tiles: a 256-thread workgroup computes 128 output rows x BN complex columns
-// (BN = 64 or 32; four waves of 64 x BN real outputs), stepping through
-// the reduction 16 complex columns at a time with double-buffered LDS and a
-// register prefetch of the next slab.  Workgroups are numbered so that all
+// spectra are embedded into the real B matrix once, when a slab is stored to
+// LDS, so fragment reads are plain loads with no arithmetic between the
+// matrix operations; each k-step's fragments are read while the previous
+// step's MFMAs run.  Tiles: a 256-thread workgroup computes 128 output rows x
+// BN complex columns (BN = 64 or 32; four waves of 64 x BN real outputs),
+// stepping through the reduction 16 complex columns at a time with
+// double-buffered LDS and a register prefetch of the next slab.  Workgroups are numbered so that all
 // tiles of one frequency run on the same XCD (hardware deals workgroups
 // round-robin over the 8 XCDs), which keeps that frequency's spectrum panel in
 // one L2.
@@ -32,9 +34,9 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int BM = 128;        // output rows per workgroup
 constexpr int BK = 16;         // complex reduction columns per slab
-constexpr int A_FWD_LD = 36;   // floats per A row (forward): 2*BK + 4 pad
+constexpr int A_FWD_LD = 34;   // floats per A row (forward): 2*BK + 2, so a fragment read hits 32 banks
 constexpr int A_ADJ_LD = 288;  // floats per A row (adjoint): 2*BM + 32 pad
-constexpr int A_FLOATS = 4608; // BM*A_FWD_LD == BK*A_ADJ_LD
+constexpr int A_FLOATS = 4608; // >= BM*A_FWD_LD, == BK*A_ADJ_LD
 
 // BN complex output columns per workgroup (64 or 32; the autotuner picks).
 template <bool ADJ, int BN>
@@ -42,11 +44,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
                                                                const float2* __restrict__ Bsrc,
                                                                float2* __restrict__ Cdst, int ncols, int tiles_m,
                                                                int tiles_n, int nblocks) {
-  constexpr int B_LD = BN + 2;        // complex per B row
+  // The spectra slab is stored already embedded as the real 2BK x 2BN matrix B (row 2k + part,
+  // column 2v + j), so a B fragment is one plain LDS read; the row stride 2BN + 16 puts the four
+  // k rows of a fragment read 16 banks apart.
+  constexpr int BRL = 2 * BN + 16;    // floats per embedded B row
   constexpr int NI = BN / 16;         // 16-real-column MFMA blocks per wave (a wave covers BN real columns)
   constexpr int B_LOADS = BK * BN / kThreads;
   __shared__ __attribute__((aligned(16))) float As[2][A_FLOATS];
-  __shared__ __attribute__((aligned(16))) float2 Bs[2][BK * B_LD];
+  __shared__ __attribute__((aligned(16))) float Br[2][2 * BK * BRL];
 
   // XCD-aware numbering: hardware block b runs on XCD b % 8; give each XCD a contiguous
   // range of logical tiles (bijective for any nblocks).
@@ -101,15 +106,23 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + kThreads * q;
-      int off;
-      if (!ADJ) off = (idx >> 3) * A_FWD_LD + 4 * (idx & 7);
-      else off = (idx >> 6) * A_ADJ_LD + 4 * (idx & 63);
-      *reinterpret_cast<float4*>(&As[buf][off]) = pa[q];
+      if (!ADJ) {  // two 8-byte stores (rows are 8-byte aligned at stride 34)
+        float* dst = &As[buf][(idx >> 3) * A_FWD_LD + 4 * (idx & 7)];
+        *reinterpret_cast<float2*>(dst) = make_float2(pa[q].x, pa[q].y);
+        *reinterpret_cast<float2*>(dst + 2) = make_float2(pa[q].z, pa[q].w);
+      } else {
+        *reinterpret_cast<float4*>(&As[buf][(idx >> 6) * A_ADJ_LD + 4 * (idx & 63)]) = pa[q];
+      }
     }
+    // real embedding of X[k][v] = c + i d:  forward rows (c, d | -d, c), adjoint rows (c, d | d, -c)
 #pragma unroll
     for (int q = 0; q < B_LOADS; ++q) {
       const int idx = tid + kThreads * q;
-      Bs[buf][(idx / BN) * B_LD + (idx % BN)] = pb[q];
+      const int rr = idx / BN, c = idx % BN;
+      const float2 z = pb[q];
+      float* row0 = &Br[buf][(2 * rr) * BRL + 2 * c];
+      *reinterpret_cast<float2*>(row0) = z;
+      *reinterpret_cast<float2*>(row0 + BRL) = ADJ ? make_float2(z.y, -z.x) : make_float2(-z.y, z.x);
     }
   };
 
@@ -119,38 +132,43 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
+  // fragments of k-step ks (real reduction rows 4 ks .. 4 ks + 3; this lane's row is 4 ks + lk)
+  struct Frag {
+    float a[4], b[NI];
+  };
+  auto read_frag = [&](Frag& F, int buf, int ks) {
+    const float* A = As[buf];
+    const float* B = Br[buf];
+    const int kr = 4 * ks + lk;  // = 2 cc + part with cc = 2 ks + lk / 2, part = lk % 2
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+      const int row = wm * 64 + mi * 16 + li;
+      F.a[mi] = ADJ ? A[(kr >> 1) * A_ADJ_LD + 2 * row + (kr & 1)] : A[row * A_FWD_LD + kr];
+    }
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) F.b[ni] = B[kr * BRL + wn * BN + ni * 16 + li];
+  };
+
   const int nslabs = (KD + BK - 1) / BK;
   load_slab(0);
   store_slab(0);
   __syncthreads();
+  Frag F[2];
   for (int sl = 0; sl < nslabs; ++sl) {
     const int buf = sl & 1;
     if (sl + 1 < nslabs) load_slab((sl + 1) * BK);
-    const float* A = As[buf];
-    const float2* Bl = Bs[buf];
+    read_frag(F[0], buf, 0);
 #pragma unroll
     for (int ks = 0; ks < BK / 2; ++ks) {
-      const int cc = 2 * ks + (lk >> 1);  // complex reduction index within the slab
-      const int part = lk & 1;
-      float a[4], bv[NI];
-#pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        const int row = wm * 64 + mi * 16 + li;
-        a[mi] = ADJ ? A[cc * A_ADJ_LD + 2 * row + part] : A[row * A_FWD_LD + 2 * cc + part];
-      }
-#pragma unroll
-      for (int ni = 0; ni < NI; ++ni) {
-        const int n = wn * (BN) + ni * 16 + li;  // real column within the tile
-        const float2 z = Bl[cc * B_LD + (n >> 1)];
-        const int jj = n & 1;
-        if (!ADJ) bv[ni] = part == 0 ? (jj == 0 ? z.x : z.y) : (jj == 0 ? -z.y : z.x);
-        else bv[ni] = part == 0 ? (jj == 0 ? z.x : z.y) : (jj == 0 ? z.y : -z.x);
-      }
+      // the next k-step's fragments are read while this step's matrix operations run
+      if (ks + 1 < BK / 2) read_frag(F[(ks + 1) & 1], buf, ks + 1);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < NI; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(F[ks & 1].a[mi], F[ks & 1].b[ni], acc[mi][ni], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (sl + 1 < nslabs) store_slab(buf ^ 1);
     __syncthreads();
