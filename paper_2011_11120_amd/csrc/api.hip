@@ -52,8 +52,9 @@ size_t store_bytes(const mdc_desc& d) {
   return 0;
 }
 
-// Product families: the streaming kernels, and the matrix-core kernels with 64- or 32-column
-// tiles (FP32) or the split-bf16 kernel (16-bit formats).
+// Product families: the streaming kernels (0), and the matrix-core kernels: FP32 with 64-column
+// (1) or 32-column (2) tiles; 16-bit formats with four waves of 64 rows (1) or eight waves of
+// 32 rows (2) per workgroup.
 enum Family { kFamGemv = 0, kFamGemm64 = 1, kFamGemm32 = 2 };
 // Default crossover without tuning: streaming kernels up to 8 columns.
 static constexpr int kGemvMaxCols = 8;
@@ -66,14 +67,15 @@ static mdc_status run_family(const mdc_op* op, int fam, int adjoint, const float
   if (d.prec == MDC_FP32)
     return gemm_launch(d, static_cast<const float2*>(op->kstore), ldk, adjoint, in, out, ncols, st,
                        fam == kFamGemm32 ? 32 : 64);
-  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, bsplit, st);
+  return gemm16_launch(d, op->kstore, op->fscale, ldk, adjoint, in, out, ncols, bsplit, fam == kFamGemm32 ? 1 : 0,
+                       st);
 }
 
 int forced_family(const mdc_op* op) {
   if (const char* e = getenv("MDC_PRODUCT")) {  // forced family (tests)
     if (!strcmp(e, "gemv")) return kFamGemv;
     if (!strcmp(e, "gemm")) return kFamGemm64;
-    if (!strcmp(e, "gemm32")) return op->d.prec == MDC_FP32 ? kFamGemm32 : kFamGemm64;
+    if (!strcmp(e, "gemm32")) return kFamGemm32;
   }
   return -1;
 }
@@ -853,8 +855,7 @@ mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* m
   for (int c : cand)
     if (c <= op->d.max_cols) nc.push_back(c);
   if (nc.empty() || nc.back() != op->d.max_cols) nc.push_back(op->d.max_cols);
-  std::vector<int> fams = {kFamGemv, kFamGemm64};
-  if (op->d.prec == MDC_FP32) fams.push_back(kFamGemm32);
+  const std::vector<int> fams = {kFamGemv, kFamGemm64, kFamGemm32};
   std::vector<int> best[2];
   for (int dir = 0; dir < 2; ++dir) {
     for (int n : nc) {
@@ -862,7 +863,7 @@ mdc_status mdc_autotune(mdc_op* op, const char* cache_path, void* stream, int* m
       float bt = 3.0e38f;
       for (int fam : fams) {
         if (fam == kFamGemv && n > 16) continue;  // streaming kernels re-read the kernel every 8 columns
-        if (fam == kFamGemm32 && n > 64) continue;
+        if (fam == kFamGemm32 && n > 64 && op->d.prec == MDC_FP32) continue;  // 32-column FP32 tiles
         const float t = time_family(op, fam, dir, n, st);
         if (t < bt) { bt = t; bf = fam; }
       }

@@ -10,9 +10,12 @@
 //           (v_mfma_f32_32x32x16_bf16).
 //   BF16:   K stored as bf16 (4 bytes); two products Khi Xhi + Khi Xlo.
 //   FP16S:  K stored as FP16 of K * 2^e_f (4 bytes, power-of-two scale per
-//           frequency); spectra split into FP16 hi + lo of X * 2^s_f, s_f from a
-//           per-frequency maximum; two products on v_mfma_f32_32x32x16_f16; both
-//           scales divided out of the result (exact, powers of two).
+//           frequency); spectra split into FP16 hi + lo of X * 2^s_fv, s_fv from the
+//           maximum of column v at frequency f; two products on
+//           v_mfma_f32_32x32x16_f16; both scales divided out of the result (exact,
+//           powers of two).  The spectra scale is per column, so the rounding of a
+//           column does not depend on the other columns of the product (requests
+//           batched together round as they would alone).
 //   FP16:   the FP16S kernel and scales, spectra rounded once to FP16 (the hi part
 //           of the split): one product Khi Xhi.
 //
@@ -25,7 +28,7 @@
 //  1. bsplit_kernel transposes the FP32 spectra [f][k][v] into split pair words
 //     [f][v][k/4][hi 4 words | lo 4 words], zero-padded to whole tiles, so every
 //     row tile stages them with plain 16-byte copies (FP16S first takes the
-//     per-frequency maximum, spec_max_kernel).
+//     per-column maxima, spec_max_kernel).
 //  2. gemm16_kernel: a 256-thread workgroup computes 256 output rows x 64 complex
 //     columns of one frequency.  Wave w owns rows 64w .. 64w + 63 (two blocks of
 //     32 rows) for all 64 complex columns, as eight 32x32 MFMA blocks: block ni
@@ -92,8 +95,10 @@ __device__ __forceinline__ float spec_scale(float mx) {
   return ldexpf(1.0f, 14 - e);
 }
 
-template <int FMT, bool ADJ>
-__global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restrict__ K,
+// RB: 32-row blocks per wave.  RB = 2: four waves of 64 rows (one per SIMD, deep register ring);
+// RB = 1: eight waves of 32 rows (two per SIMD, half the registers each).
+template <int FMT, bool ADJ, int RB>
+__global__ __launch_bounds__(BM / (32 * RB) * 64, 1) void gemm16_kernel(const char* __restrict__ K,
                                                              const float* __restrict__ fscale,
                                                              const float* __restrict__ bmax, int ns, int nr, int ldk,
                                                              const unsigned int* __restrict__ Bp, int KG, int NCP,
@@ -104,7 +109,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
   constexpr bool F16 = FMT == MDC_FP16S || FMT == MDC_FP16;
   constexpr bool ONE = FMT == MDC_FP16;  // spectra hi part only: one product
   using frag = typename std::conditional<F16, h8v, bf8v>::type;
-  constexpr int NA = X2 ? 8 : 4;  // u4v per lane per k-step: 2 row blocks x 2 k-halves x (hi, lo | one)
+  constexpr int NTH = BM / (32 * RB) * 64;  // threads per workgroup
+  constexpr int NA = (X2 ? 2 : 1) * 2 * RB;  // u4v per lane per k-step: RB row blocks x 2 k-halves (x hi, lo)
+  constexpr int NB = 1024 / NTH;             // 16-byte spectra pieces per thread per slab
 
   const int b = blockIdx.x;
   const int q8 = nblocks >> 3, rem = nblocks & 7, xcd = b & 7;
@@ -128,18 +135,18 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
   const int nsteps = KG >> 2;  // 16-column k-steps, a multiple of 6
   const int nslabs = nsteps >> 1;
 
-  // this lane's two output rows (kernel rows forward, kernel columns adjoint), clamped
-  size_t aoff[2];
+  // this lane's RB output rows (kernel rows forward, kernel columns adjoint), clamped
+  size_t aoff[RB];
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
-    const int rr = min(m0 + wave * 64 + rb * 32 + l32, M - 1);
+  for (int rb = 0; rb < RB; ++rb) {
+    const int rr = min(m0 + wave * 32 * RB + rb * 32 + l32, M - 1);
     aoff[rb] = !ADJ ? (size_t)rr * rowb : (X2 ? (size_t)(rr >> 2) * 32 + (rr & 3) * 4 : (size_t)rr * 4);
   }
   // kernel fragments of k-step j: r[q] (q = 2 rb + h) holds the lane's four reduction
   // indices 16 j + 8 h + 4 kh .. + 3 of row block rb (X2: r[2q] hi, r[2q + 1] lo)
   auto load_a = [&](int j, u4v (&r)[NA]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2 * RB; ++q) {
       const int h = q & 1, rb = q >> 1;
       const int g = 4 * min(j, nsteps - 1) + 2 * h + kh;  // group of four reduction indices
       if constexpr (!ADJ) {
@@ -159,13 +166,13 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
       }
     }
   };
-  // split spectra of one slab: 64 columns x 8 groups x (hi, lo), four 16-byte pieces per thread
-  u4v pb[4];
+  // split spectra of one slab: 64 columns x 8 groups x (hi, lo), NB 16-byte pieces per thread
+  u4v pb[NB];
   auto load_b = [&](int sl) {
     const int g0 = min(sl, nslabs - 1) * (BK / 4);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + kThreads * q;
+    for (int q = 0; q < NB; ++q) {
+      const int idx = tid + NTH * q;
       const int v = idx >> 4, gi = (idx & 15) >> 1, half = idx & 1;
       pb[q] = *reinterpret_cast<const u4v*>(Bf + ((size_t)v * KG + g0 + gi) * 8 + half * 4);
     }
@@ -173,8 +180,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
   // both embedded variants: forward (c, -d) | (d, c), adjoint (e, f) | (f, -e)
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + kThreads * q;
+    for (int q = 0; q < NB; ++q) {
+      const int idx = tid + NTH * q;
       const int v = idx >> 4, gi = (idx & 15) >> 1, half = idx & 1;
       const u4v w = pb[q];
       const u4v sw = u4v{swap16(w.x), swap16(w.y), swap16(w.z), swap16(w.w)};
@@ -199,9 +206,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
     }
   };
 
-  f16v acc[2][4];
+  f16v acc[RB][4];
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
   };
   auto compute = [&](const u4v (&r)[NA], const Frags& F, int h) {
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const int q = 2 * rb + h;
       const frag ah = __builtin_bit_cast(frag, r[X2 ? 2 * q : q]);
 #pragma unroll
@@ -265,18 +272,18 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
     }
   }
 
-  // FP16: divide out the kernel's and the spectra's power-of-two scales
-  const float osc = F16 ? 1.0f / (fscale[f] * spec_scale(bmax[f])) : 1.0f;
   // D of a 32x32 block: column = lane % 32, row = 8 (e / 4) + 4 (lane / 32) + e % 4
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) {
       const int v = n0 + (ni >> 1) * 32 + l32;
       if (v >= ncols) continue;
+      // FP16: divide out the kernel's and the column's power-of-two scales
+      const float osc = F16 ? 1.0f / (fscale[f] * spec_scale(bmax[(size_t)f * NCP + v])) : 1.0f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int row = m0 + wave * 64 + rb * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        const int row = m0 + wave * 32 * RB + rb * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
         if (row < M) Cf[((size_t)row * ncols + v) * 2 + (ni & 1)] = acc[rb][ni][e] * osc;
       }
     }
@@ -285,8 +292,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm16_kernel(const char* __restr
 // Split spectra X[f][k][ncols] (complex FP32) into Bp[f][v][g][8]: words 0-3 the hi pair
 // words (re | im << 16) of k = 4g..4g+3, words 4-7 the lo pair words, v < NCP, g < KG, zero
 // outside [KD) x [ncols).  bf16: hi = RNE(x), lo = RNE(x - hi).  FP16 (F16): the same of
-// x * s_f with s_f = spec_scale(bmax[f]).  One workgroup transposes a 64 (k) x 64 (v) tile
-// through LDS.
+// x * s_fv with s_fv = spec_scale(bmax[f][v]).  One workgroup transposes a 64 (k) x 64 (v)
+// tile through LDS.
 template <bool F16>
 __global__ __launch_bounds__(kThreads) void bsplit_kernel(const float2* __restrict__ X, int KD, int ncols, int KG,
                                                           int NCP, const float* __restrict__ bmax,
@@ -303,13 +310,13 @@ __global__ __launch_bounds__(kThreads) void bsplit_kernel(const float2* __restri
     tile[kk][v] = (k < KD && c < ncols) ? Xf[(size_t)k * ncols + c] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  const float sc = F16 ? spec_scale(bmax[f]) : 1.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int task = tid + kThreads * i;
     const int g = task & 15, v = task >> 4;
     const int gg = (k0 >> 2) + g;
     if (gg >= KG) continue;
+    const float sc = F16 ? spec_scale(bmax[(size_t)f * NCP + v0 + v]) : 1.0f;
     unsigned int hi[4], lo[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -333,39 +340,55 @@ __global__ void zero_floats(float* __restrict__ p, int n) {
   if (i < n) p[i] = 0.f;
 }
 
-// bmax[f] = max |re|, |im| over the spectrum slice of frequency f (bmax zeroed first;
-// the maximum of non-negative floats is order independent, so the atomic is exact).
-__global__ __launch_bounds__(kThreads) void spec_max_kernel(const float2* __restrict__ X, size_t per_f,
-                                                            float* __restrict__ bmax) {
-  __shared__ float part[kThreads / 64];
+// bmax[f][v] = max |re|, |im| over column v of the spectrum slice of frequency f (X[f][k][v],
+// k < KD), v < ncols (bmax zeroed first; columns past ncols keep 0).  A workgroup covers 64
+// columns of one frequency and one chunk of kchunk reduction rows (its four waves stride over
+// them); chunks combine by an atomic maximum, which is exact and order independent for
+// non-negative floats compared as integers.
+__global__ __launch_bounds__(kThreads) void spec_max_kernel(const float2* __restrict__ X, int KD, int ncols, int NCP,
+                                                            int kchunk, float* __restrict__ bmax) {
+  __shared__ float part[kThreads / 64][64];
   const int f = blockIdx.y;
-  const float2* Xf = X + (size_t)f * per_f;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int v = blockIdx.x * 64 + lane;
+  const float2* Xf = X + (size_t)f * KD * ncols;
+  const int k0 = blockIdx.z * kchunk, k1 = min(KD, k0 + kchunk);
   float m = 0.f;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < per_f; i += (size_t)gridDim.x * kThreads) {
-    const float2 z = Xf[i];
-    m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  if (v < ncols)
+    for (int k = k0 + wave; k < k1; k += kThreads / 64) {
+      const float2 z = Xf[(size_t)k * ncols + v];
+      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+    }
+  part[wave][lane] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, part[w]);
-    atomicMax(reinterpret_cast<unsigned int*>(bmax) + f, __float_as_uint(m));
+  if (wave == 0 && v < ncols) {
+    m = fmaxf(fmaxf(part[0][lane], part[1][lane]), fmaxf(part[2][lane], part[3][lane]));
+    atomicMax(reinterpret_cast<unsigned int*>(bmax) + (size_t)f * NCP + v, __float_as_uint(m));
   }
 }
+
+size_t split_cols(const mdc_desc& d) { return (size_t)(d.max_cols + BN - 1) / BN * BN; }
 
 // Bytes of the split spectra: nfmax x (max_cols rounded up to BN) x (reduction rounded up to
 // KSTEP_PAD) x 8.
 size_t split_data_bytes(const mdc_desc& d) {
-  const size_t ncp = (size_t)(d.max_cols + BN - 1) / BN * BN;
   const size_t kdp = (size_t)((d.ns > d.nr ? d.ns : d.nr) + KSTEP_PAD - 1) / KSTEP_PAD * KSTEP_PAD;
-  return (size_t)d.nfmax * ncp * kdp * 8;
+  return (size_t)d.nfmax * split_cols(d) * kdp * 8;
 }
 
+template <int FMT, bool ADJ, int RB>
+void launch_gemm16(const char* K, const float* fscale, const float* bmax, const mdc_desc& d, int ldk,
+                   const unsigned int* bsplit, int KG, int NCP, float2* out, int ncols, int tiles_m, int tiles_n,
+                   int nblocks, hipStream_t st) {
+  constexpr int NTH = BM / (32 * RB) * 64;
+  hipLaunchKernelGGL((gemm16_kernel<FMT, ADJ, RB>), dim3(nblocks), dim3(NTH), 0, st, K, fscale, bmax, d.ns, d.nr, ldk,
+                     bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks);
+}
+
+// variant 0: four waves of 64 rows per workgroup; variant 1: eight waves of 32 rows.
 template <int FMT>
 mdc_status launch_fmt(const mdc_desc& d, const char* K, const float* fscale, int ldk, int adjoint, const float2* in,
-                      float2* out, int ncols, unsigned int* bsplit, hipStream_t st) {
+                      float2* out, int ncols, unsigned int* bsplit, int variant, hipStream_t st) {
   const int M = adjoint ? d.nr : d.ns;
   const int KD = adjoint ? d.ns : d.nr;
   const int tiles_m = (M + BM - 1) / BM;
@@ -378,22 +401,24 @@ mdc_status launch_fmt(const mdc_desc& d, const char* K, const float* fscale, int
   float* bmax = reinterpret_cast<float*>(reinterpret_cast<char*>(bsplit) + align_up(split_data_bytes(d), 256));
   const dim3 sgrid((KG * 4 + 63) / 64, NCP / 64, d.nfmax);
   if constexpr (FMT == MDC_FP16S || FMT == MDC_FP16) {
-    hipLaunchKernelGGL(zero_floats, dim3((d.nfmax + 255) / 256), dim3(256), 0, st, bmax, d.nfmax);
-    const size_t per_f = (size_t)KD * ncols;
-    const int bx = (int)std::min<size_t>(64, (per_f + kThreads * 16 - 1) / (kThreads * 16));
-    hipLaunchKernelGGL(spec_max_kernel, dim3(bx, d.nfmax), dim3(kThreads), 0, st, in, per_f, bmax);
+    const int nmax = d.nfmax * NCP;
+    hipLaunchKernelGGL(zero_floats, dim3((nmax + 255) / 256), dim3(256), 0, st, bmax, nmax);
+    const int kchunk = 256, nch = (KD + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL(spec_max_kernel, dim3(NCP / 64, d.nfmax, nch), dim3(kThreads), 0, st, in, KD, ncols, NCP,
+                       kchunk, bmax);
     hipLaunchKernelGGL(bsplit_kernel<true>, sgrid, dim3(kThreads), 0, st, in, KD, ncols, KG, NCP, bmax, bsplit);
   } else {
     hipLaunchKernelGGL(bsplit_kernel<false>, sgrid, dim3(kThreads), 0, st, in, KD, ncols, KG, NCP, bmax, bsplit);
   }
   mdc_status s = check_launch("bsplit_kernel");
   if (s != MDC_OK) return s;
-  if (adjoint)
-    hipLaunchKernelGGL((gemm16_kernel<FMT, true>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, bmax, d.ns, d.nr,
-                       ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks);
-  else
-    hipLaunchKernelGGL((gemm16_kernel<FMT, false>), dim3(nblocks), dim3(kThreads), 0, st, K, fscale, bmax, d.ns,
-                       d.nr, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks);
+  if (variant == 1) {
+    if (adjoint) launch_gemm16<FMT, true, 1>(K, fscale, bmax, d, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks, st);
+    else launch_gemm16<FMT, false, 1>(K, fscale, bmax, d, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks, st);
+  } else {
+    if (adjoint) launch_gemm16<FMT, true, 2>(K, fscale, bmax, d, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks, st);
+    else launch_gemm16<FMT, false, 2>(K, fscale, bmax, d, ldk, bsplit, KG, NCP, out, ncols, tiles_m, tiles_n, nblocks, st);
+  }
   return check_launch("gemm16_kernel");
 }
 
@@ -419,17 +444,17 @@ mdc_status fp16_scales_launch(float* fscale, int nfmax, hipStream_t st) {
 }
 
 size_t gemm16_split_bytes(const mdc_desc& d) {
-  return align_up(split_data_bytes(d), 256) + align_up((size_t)d.nfmax * 4, 256);
+  return align_up(split_data_bytes(d), 256) + align_up((size_t)d.nfmax * split_cols(d) * 4, 256);
 }
 
 mdc_status gemm16_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint,
-                         const float2* in, float2* out, int ncols, unsigned int* bsplit, hipStream_t st) {
+                         const float2* in, float2* out, int ncols, unsigned int* bsplit, int variant, hipStream_t st) {
   const char* k = static_cast<const char*>(K);
   switch (d.prec) {
-    case MDC_FP16S: return launch_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
-    case MDC_FP16: return launch_fmt<MDC_FP16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
-    case MDC_BF16: return launch_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
-    case MDC_BF16X2: return launch_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, st);
+    case MDC_FP16S: return launch_fmt<MDC_FP16S>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, variant, st);
+    case MDC_FP16: return launch_fmt<MDC_FP16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, variant, st);
+    case MDC_BF16: return launch_fmt<MDC_BF16>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, variant, st);
+    case MDC_BF16X2: return launch_fmt<MDC_BF16X2>(d, k, fscale, ldk, adjoint, in, out, ncols, bsplit, variant, st);
     default: return fail(MDC_EINVAL, "gemm16: not a 16-bit format");
   }
 }

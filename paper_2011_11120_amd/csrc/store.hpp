@@ -101,8 +101,9 @@ mdc_status gemv_launch(const mdc_desc& d, const void* K, const float* fscale, in
 mdc_status fp16_scales_launch(float* fscale, int nfmax, hipStream_t st);
 // bsplit: workspace of gemm16_split_bytes(d) bytes receiving the split spectra of each launch.
 size_t gemm16_split_bytes(const mdc_desc& d);
+// variant 0: four waves of 64 output rows per workgroup; 1: eight waves of 32 rows.
 mdc_status gemm16_launch(const mdc_desc& d, const void* K, const float* fscale, int ldk, int adjoint,
-                         const float2* in, float2* out, int ncols, unsigned int* bsplit, hipStream_t st);
+                         const float2* in, float2* out, int ncols, unsigned int* bsplit, int variant, hipStream_t st);
 mdc_status gemm_launch(const mdc_desc& d, const float2* K, int ldk, int adjoint, const float2* in, float2* out,
                        int ncols, hipStream_t st, int bn);
 

@@ -130,3 +130,47 @@ def test_marchenko_lsqr_low_precision(mdcmod, prec):
     print(f"marchenko lsqr {prec}: model error {err:.2e}", flush=True)
     assert err < 1e-3
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16s", "fp16"])
+def test_fp16_spectra_scale_is_per_column(mdcmod, monkeypatch, prec):
+    """On the FP16 matrix cores each column's spectra get their own power-of-two scale, so a
+    column's result does not depend on the magnitude of the columns batched with it: the first
+    columns of a product [A | 2^20 B] equal the product of A alone, bit for bit."""
+    monkeypatch.setenv("MDC_PRODUCT", "gemm")
+    nt, nfmax, ns, nr, na, nb = 128, 30, 140, 100, 5, 11
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=23)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=na + nb, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    xa = synth.gaussian((nt, nr, na), seed=24)
+    xb = synth.gaussian((nt, nr, nb), seed=25) * 2.0 ** 20
+    for adjoint in (False, True):
+        n_in = ns if adjoint else nr
+        a = synth.gaussian((nt, n_in, na), seed=26) if adjoint else xa
+        b = synth.gaussian((nt, n_in, nb), seed=27) * 2.0 ** 20 if adjoint else xb
+        apply = op.adjoint if adjoint else op.forward
+        alone = host(apply(dev(a)))
+        mixed = host(apply(dev(np.concatenate([a, b], axis=2))))
+        assert np.array_equal(mixed[:, :, :na], alone)
+        ref = (om.mdc_adjoint if adjoint else om.mdc_forward)(K, a)
+        assert relmax(alone, ref) < TOL[prec]
+    op.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16", "fp16"])
+@pytest.mark.parametrize("nv", [9, 64, 130])
+def test_eight_wave_gemm16_matches_oracle(mdcmod, monkeypatch, prec, nv):
+    """The 16-bit matrix-core product with eight waves of 32 rows per workgroup (family 2),
+    forced at several widths (one, one full and three column tiles), against the oracle."""
+    monkeypatch.setenv("MDC_PRODUCT", "gemm32")
+    nt, nfmax, ns, nr = 128, 24, 300, 230
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=31 + nv)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    x = synth.gaussian((nt, nr, nv), seed=32)
+    y = synth.gaussian((nt, ns, nv), seed=33)
+    ef = relmax(host(op.forward(dev(x))), om.mdc_forward(K, x))
+    ea = relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y))
+    print(f"eight-wave gemm16 {prec} nv={nv}: forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef < TOL[prec] and ea < TOL[prec]
+    op.close()
