@@ -52,16 +52,31 @@ def algorithmic_bytes(nt, nfmax, n, nv):
     return kernel, kernel + spectra, kernel + vectors
 
 
+def host_cpu():
+    """CPU model and core counts of the host the baseline runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(spec, x, y, target_s: float = 8.0):
-    """FP64 oracle on a frequency subset; time scaled to all bins."""
+    """FP64 oracle on a frequency subset; time scaled to all bins.  Timed with the BLAS library's
+    own thread count and again on one thread; the figure per run is the median repeat."""
+    import statistics
+
     import numpy as np
     from oracle import mdc as om
     from paper_2011_11120_amd import synth
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     nsub = 10
     bins = np.linspace(0, spec.nfmax - 1, nsub).astype(int)
     idx = np.arange(spec.n)
@@ -73,16 +88,22 @@ def cpu_baseline(spec, x, y, target_s: float = 8.0):
         om.mdc_forward(Ksub, x)
         om.mdc_adjoint(Ksub, y)
 
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        one()
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or reps >= 200:
-            break
-    t_sample = el / reps
-    t_full = t_sample * spec.nfmax / nsub
-    return t_full, threads, f"{nsub} of {spec.nfmax} bins (FP64, {reps} repeats), scaled by bins"
+    def timed(budget_s):
+        reps, t0 = [], time.perf_counter()
+        while True:
+            a = time.perf_counter()
+            one()
+            reps.append(time.perf_counter() - a)
+            if time.perf_counter() - t0 >= budget_s or len(reps) >= 200:
+                break
+        return statistics.median(reps) * spec.nfmax / nsub, statistics.mean(reps) * spec.nfmax / nsub, len(reps)
+
+    med_all, mean_all, n_all = timed(target_s)
+    with threadpool_limits(limits=1):
+        med_one, mean_one, n_one = timed(target_s)
+    return {"median_s": med_all, "mean_s": mean_all, "repeats": n_all, "threads": threads,
+            "one_thread": {"median_s": med_one, "mean_s": mean_one, "repeats": n_one},
+            "sample": f"{nsub} of {spec.nfmax} bins (FP64), scaled by bins", "host": host_cpu()}
 
 
 COPY_BYTES = 256 * 1024 * 1024
@@ -160,8 +181,15 @@ def main():
     ap.add_argument("--c5-light", type=float, default=0.0,
                     help="c5: light-load Poisson stream at this fraction of the format's capacity (0: none)")
     ap.add_argument("--c5-light-requests", type=int, default=24, help="c5: requests of the light-load stream")
+    ap.add_argument("--c5-alone", type=int, default=0,
+                    help="c5: solve this many sampled requests of a closed-loop run again alone and compare")
+    ap.add_argument("--c5-closed-only", action="store_true", help="c5: closed loop only (no Poisson streams)")
     ap.add_argument("--prec", choices=["fp32", "fp16s", "bf16", "bf16x2", "fp16"], default="fp32",
                     help="kernel storage format for the c3/c4 workloads")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: skip the matrix-core and served-stream legs of the line")
+    ap.add_argument("--leg-requests", type=int, default=12, help="served-stream leg: requests per format")
+    ap.add_argument("--leg-skip", type=int, default=2, help="served-stream leg: first completions excluded")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -252,9 +280,14 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        t_full, threads, sample = cpu_baseline(spec, x_h, y_h)
-        cpu = {"value": round(step_bytes / t_full / 1e9, 4), "unit": "GB/s", "cores": threads,
-               "kind": "oracle", "sample": sample, "s_per_step": round(t_full, 3)}
+        cb = cpu_baseline(spec, x_h, y_h)
+        cpu = {"value": round(step_bytes / cb["median_s"] / 1e9, 4), "unit": "GB/s", "cores": cb["threads"],
+               "kind": "oracle", "sample": cb["sample"] + f", median of {cb['repeats']} repeats",
+               "s_per_step_median": round(cb["median_s"], 3), "s_per_step_mean": round(cb["mean_s"], 3),
+               "one_core": {"value": round(step_bytes / cb["one_thread"]["median_s"] / 1e9, 4), "unit": "GB/s",
+                            "s_per_step_median": round(cb["one_thread"]["median_s"], 3),
+                            "repeats": cb["one_thread"]["repeats"]},
+               "host": cb["host"]}
 
     out = {
         "metric": "MDC fwd/adj HBM GB/s & MFMA % peak; served LSQR solves/s, p50/p99 latency",
@@ -285,11 +318,39 @@ def main():
         "cpu_baseline": cpu,
         "wall_s": round(wall, 3),
     }
-    print(json.dumps(out), flush=True)
     op.close()
+    del op, x, y, xo, yo
+    torch.cuda.empty_cache()
+    if not args.no_legs and not args.copy_calibration:
+        out["legs"] = headline_legs(args)
+    print(json.dumps(out), flush=True)
 
 
-def bench_c3(args):
+def headline_legs(args):
+    """The other two legs of the headline metric, measured in the same run at reduced counts:
+    the matrix-core product of the 64-point workload (FP32 MFMA fraction of peak) and the served
+    stream (closed-loop solves/s and p50/p99 per format).  The full-count records of both are
+    produced by --workload c3 / c5."""
+    import argparse as _ap
+    legs = {}
+    print("leg: 64-point matrix-core product", file=sys.stderr, flush=True)
+    c3 = bench_c3(_ap.Namespace(prec="fp32", steps=5, warmup=1), emit=False)
+    legs["mfma_64_points_fp32"] = {"workload": c3["workload"], "product_ms": c3["product_ms"],
+                                   "roofline": c3["roofline"], "steps": 5}
+    print("leg: served stream", file=sys.stderr, flush=True)
+    ns = _ap.Namespace(requests=args.leg_requests, skip=args.leg_skip, c5_precs="fp32,fp16s", c5_max_cols=384,
+                       c5_sublattice=6, c5_rate=None, c5_light=0.0, c5_light_requests=0, c5_closed_only=True,
+                       c5_alone=0)
+    c5 = bench_c5(ns, emit=False)
+    legs["served_lsqr"] = {"workload": c5["workload"],
+                           "closed_loop": {p: {k: v["closed"][k] for k in ("solves_per_s", "p50_s", "p99_s",
+                                                                            "latency_samples", "max_active")}
+                                           for p, v in c5["results"].items()},
+                           "solution_rel_diff_fp16s_vs_fp32": c5["solution_rel_diff_vs_fp32"].get("fp16s")}
+    return legs
+
+
+def bench_c3(args, emit=True):
     """64 virtual points: nt=1024, nfmax=300, ns=nr=60x60=3600, complex64 kernel (31.1 GB), FP32 MFMA."""
     import numpy as np
     import torch
@@ -353,8 +414,12 @@ def bench_c3(args):
            "stage_ms_per_launch": {k: round(ms_stage[i] / max(1, cnt[i]), 4) for i, k in
                                    enumerate(["rfft", "product_fwd", "product_adj", "irfft"])},
            "fft_roofline": fft_roof}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
     op.close()
+    del op, x, y, xo, yo
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_c4(args, niter=30):
@@ -474,7 +539,7 @@ def c5_leg(mdc, op, spec, reqs, arena_t, args, rate=None, keep=()):
                          "deferred_wait_s": round(ps["deferred_s"], 3)}}, kept
 
 
-def bench_c5(args):
+def bench_c5(args, emit=True):
     """Served stream: 100 x 100 traces, nfmax=200, nt=1024; FP32 vs 16-bit kernel storage.
 
     Per format: a closed loop (6 outstanding requests) gives the capacity; a Poisson stream at 0.7 x
@@ -505,16 +570,28 @@ def bench_c5(args):
               f"({levels / 1e9:.1f} GB lattice levels)", file=sys.stderr, flush=True)
         res = {"kernel_GB": round(op.resident.numel() / 1e9, 1), "arena_GB": round(arena / 1e9, 1),
                "lattice_levels_GB": round(levels / 1e9, 1)}
-        res["closed"], sols[prec] = c5_leg(mdc, op, spec, reqs, arena_t, args, keep=(0, 1))
+        picks = list(range(0, len(reqs), max(1, len(reqs) // args.c5_alone)))[:args.c5_alone] if args.c5_alone else []
+        res["closed"], kept = c5_leg(mdc, op, spec, reqs, arena_t, args, keep=tuple(sorted({0, 1, *picks})))
+        sols[prec] = {k: kept[k] for k in (0, 1)}
         cap = res["closed"]["solves_per_s"]
         if prec == "fp32" and rate32 is None:
             rate32 = 0.7 * cap
-        if rate32 is not None:
+        if getattr(args, "c5_closed_only", False):
+            pass
+        elif rate32 is not None:
             res["poisson_fp32_rate"], _ = c5_leg(mdc, op, spec, reqs, arena_t, args, rate=rate32)
             res["poisson_fp32_rate"]["rate_per_s"] = round(rate32, 4)
-        if prec != "fp32":
+        if prec != "fp32" and not getattr(args, "c5_closed_only", False):
             res["poisson_own_rate"], _ = c5_leg(mdc, op, spec, reqs, arena_t, args, rate=0.7 * cap)
             res["poisson_own_rate"]["rate_per_s"] = round(0.7 * cap, 4)
+        if picks:  # sampled requests of the closed loop solved again alone
+            errs = {}
+            for k in picks:
+                _, alone = c5_leg(mdc, op, spec, [reqs[k]], arena_t, args, keep=(0,))
+                a, m = alone[0], kept[k]
+                errs[k] = float(torch.linalg.vector_norm(m - a) / torch.linalg.vector_norm(a))
+            res["alone_vs_mix"] = {"requests": picks, "rel_diff": errs, "max_rel_diff": max(errs.values())}
+        del kept
         if args.c5_light > 0:
             light = reqs[:args.c5_light_requests]
             res["poisson_light"], _ = c5_leg(mdc, op, spec, light, arena_t, args, rate=args.c5_light * cap)
@@ -527,13 +604,16 @@ def bench_c5(args):
     for p in precs[1:]:
         diff[p] = {k: float(torch.linalg.vector_norm(sols[p][k] - sols[precs[0]][k]) /
                             torch.linalg.vector_norm(sols[precs[0]][k])) for k in sols[p]}
-    print(json.dumps({"workload": "served Marchenko LSQR, 100x100 traces, nfmax=200, nt=1024, "
-                                  f"{len(reqs)} requests (nv 1-64, 10-60 it, d 1/2/4), first {args.skip} "
-                                  "completions excluded from p50/p99",
-                      "sublattice": args.c5_sublattice, "column_budget": args.c5_max_cols,
-                      "requests": [{k: r[k] for k in ("nv", "niter", "decim")} for r in reqs],
-                      "results": results, "poisson_rate_fp32_capacity_x0.7": rate32,
-                      "solution_rel_diff_vs_" + precs[0]: diff}), flush=True)
+    out = {"workload": "served Marchenko LSQR, 100x100 traces, nfmax=200, nt=1024, "
+                       f"{len(reqs)} requests (nv 1-64, 10-60 it, d 1/2/4), first {args.skip} "
+                       "completions excluded from p50/p99",
+           "sublattice": args.c5_sublattice, "column_budget": args.c5_max_cols,
+           "requests": [{k: r[k] for k in ("nv", "niter", "decim")} for r in reqs],
+           "results": results, "poisson_rate_fp32_capacity_x0.7": rate32,
+           "solution_rel_diff_vs_" + precs[0]: diff}
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
