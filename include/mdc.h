@@ -326,7 +326,10 @@ mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes);
 /* Arena bytes serve_create reserves for the lattice level of decimation 2 or 4 (index tables
  * and the gathered kernel in the op's storage format). */
 mdc_status serve_level_bytes(const mdc_op* op, int decim, size_t* bytes);
-/* arena: caller-owned device buffer (256-byte aligned) for request slots. */
+/* arena: caller-owned device buffer (256-byte aligned) for the lattice levels (first) and the
+ * request slots.  The op's kernel must be loaded and its load synchronised: the lattice levels
+ * are gathered from it, on the server's stream, before the call returns.  MDC_ENOMEM when the
+ * arena cannot hold the levels asked for. */
 mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t arena_bytes, mdc_server** out);
 /* Queue a request (MDC_ENOMEM if it can never fit the arena or the column budget). Buffers
  * must be ready (their producers synchronised) before the call. */
