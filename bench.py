@@ -264,6 +264,17 @@ def main():
     mdc.mdc_profile(op.handle, False)
     ms_stage, cnt = mdc.mdc_profile_read(op.handle)
     ms_step_profiled = ev2.elapsed_time(ev3) / args.steps
+    # third pass: one event pair per step, for the median and spread of the step time
+    per_step = []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    per_step = sorted(a.elapsed_time(b) for a, b in evs)
+    ms_median = per_step[len(per_step) // 2] if len(per_step) % 2 else 0.5 * (
+        per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
 
     kbytes, prod_bytes, apply_bytes = algorithmic_bytes(spec.nt, spec.nfmax, n, nv)
     step_bytes = 2 * apply_bytes
@@ -297,6 +308,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(ms_median, 4),
+        "ms_per_step_min_max": [round(per_step[0], 4), round(per_step[-1], 4)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
