@@ -17,13 +17,13 @@
 // spectra are embedded into the real B matrix once, when a slab is stored to
 // LDS, so fragment reads are plain loads with no arithmetic between the
 // matrix operations; each k-step's fragments are read while the previous
-// step's MFMAs run.  Tiles: a 256-thread workgroup computes 128 output rows x
-// BN complex columns (BN = 64 or 32; four waves of 64 x BN real outputs),
-// stepping through the reduction 16 complex columns at a time with
-// double-buffered LDS and a register prefetch of the next slab.  Workgroups are numbered so that all
-// tiles of one frequency run on the same XCD (hardware deals workgroups
-// round-robin over the 8 XCDs), which keeps that frequency's spectrum panel in
-// one L2.
+// step's MFMAs run, the reads interleaved with them. Tiles: a 256-thread
+// workgroup computes 128 output rows x BN complex columns (BN = 64 or 32; four
+// waves of 64 x BN real outputs), stepping through the reduction 16 complex
+// columns at a time with double-buffered LDS and a register prefetch of the
+// next slab. Workgroups are numbered so that all tiles of one frequency run on
+// the same XCD (hardware deals workgroups round-robin over the 8 XCDs), which
+// keeps that frequency's spectrum panel in one L2.
 #include "common.hpp"
 
 namespace mdc {
@@ -149,6 +149,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
     for (int ni = 0; ni < NI; ++ni) F.b[ni] = B[kr * BRL + wn * BN + ni * 16 + li];
   };
 
+  // A wave whose 64 rows all lie past the last output row (in the last row tile when M is not a
+  // multiple of BM) skips the matrix operations; it still takes part in the slab loads.
+  const bool active = m0 + __builtin_amdgcn_readfirstlane(wm) * 64 < M;
   const int nslabs = (KD + BK - 1) / BK;
   load_slab(0);
   store_slab(0);
@@ -157,18 +160,28 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_f32_kernel(const float2* __r
   for (int sl = 0; sl < nslabs; ++sl) {
     const int buf = sl & 1;
     if (sl + 1 < nslabs) load_slab((sl + 1) * BK);
-    read_frag(F[0], buf, 0);
+    if (active) {
+      read_frag(F[0], buf, 0);
 #pragma unroll
-    for (int ks = 0; ks < BK / 2; ++ks) {
-      // the next k-step's fragments are read while this step's matrix operations run
-      if (ks + 1 < BK / 2) read_frag(F[(ks + 1) & 1], buf, ks + 1);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int ks = 0; ks < BK / 2; ++ks) {
+        // the next k-step's fragments are read while this step's matrix operations run, one
+        // LDS read issued between every MPR of them
+        if (ks + 1 < BK / 2) read_frag(F[(ks + 1) & 1], buf, ks + 1);
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < NI; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(F[ks & 1].a[mi], F[ks & 1].b[ni], acc[mi][ni], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
+          for (int ni = 0; ni < NI; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(F[ks & 1].a[mi], F[ks & 1].b[ni], acc[mi][ni], 0, 0, 0);
+        if (ks + 1 < BK / 2) {
+          constexpr int NR = 4 + NI, MPR = 4 * NI / NR;  // fragment reads, matrix operations per read
+#pragma unroll
+          for (int i = 0; i < NR; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0);  // matrix operations
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // one LDS read
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     if (sl + 1 < nslabs) store_slab(buf ^ 1);
     __syncthreads();

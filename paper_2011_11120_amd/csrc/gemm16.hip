@@ -218,9 +218,16 @@ __global__ __launch_bounds__(BM / (32 * RB) * 64, 1) void gemm16_kernel(const ch
     if constexpr (F16) return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bb, c, 0, 0, 0);
     else return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, c, 0, 0, 0);
   };
+  // Row blocks that hold no output row (the last row tile when M is not a multiple of BM)
+  // skip their matrix operations; their clamped loads and the cooperative spectra staging
+  // run as in every other block.
+  bool rvalid[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) rvalid[rb] = m0 + __builtin_amdgcn_readfirstlane(wave) * 32 * RB + rb * 32 < M;
   auto compute = [&](const u4v (&r)[NA], const Frags& F, int h) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
+      if (!rvalid[rb]) continue;
       const int q = 2 * rb + h;
       const frag ah = __builtin_bit_cast(frag, r[X2 ? 2 * q : q]);
 #pragma unroll
