@@ -242,6 +242,7 @@ GEMM_SHAPES = [
     (256, 60, 300, 200, 64),    # one full 64-column tile
     (128, 30, 200, 130, 65),    # two column tiles, second with one column
     (64, 20, 17, 300, 130),     # three column tiles, tiny ns
+    (64, 16, 256, 128, 24),     # whole 128-row tiles in both directions (no idle waves)
 ]
 
 

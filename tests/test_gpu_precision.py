@@ -43,7 +43,8 @@ def mdcmod(gpu):
 
 
 SHAPES = [(64, 20, 40, 40, 1), (128, 40, 130, 98, 3), (128, 40, 129, 257, 9),
-          (256, 60, 300, 200, 64), (128, 30, 200, 130, 65), (64, 20, 70, 30, 17)]
+          (256, 60, 300, 200, 64), (128, 30, 200, 130, 65), (64, 20, 70, 30, 17),
+          (64, 16, 512, 256, 24)]  # whole 256-row tiles in both directions (no idle row blocks)
 
 
 @pytest.mark.parametrize("prec", ["bf16x2", "fp16s", "bf16", "fp16"])
