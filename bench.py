@@ -164,8 +164,9 @@ def main():
         return write_traffic(sys.argv[2], sys.argv[3])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: c2 100 forward + adjoint steps, c3 20, c4 3 solves per grid)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default: c2 10, c3 2, c4 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: single-point GEMV workload (default line); c3: 64-point matrix-core workload; "
@@ -193,6 +194,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    # c2: forward and adjoint each applied 100 times after 10 warm-up steps; c3: 20 steps
+    defaults = {"c2": (100, 10), "c3": (20, 2), "c4": (3, 1), "c5": (1, 0)}[args.workload]
+    if args.steps is None:
+        args.steps = defaults[0]
+    if args.warmup is None:
+        args.warmup = defaults[1]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the MDC path here is single-GPU "
               "(frequency sharding across GPUs is a design, not built)", file=sys.stderr)
