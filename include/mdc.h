@@ -267,7 +267,10 @@ mdc_status lsqr_query_sizes(const mdc_op* op, const lsqr_desc* ld, size_t* work_
  * transform (environment MDC_LSQR_FUSE=0 runs them as separate vector passes:
  * the same per-element arithmetic, norms summed in a different grouping), and
  * iterations after the first replay a captured graph (MDC_LSQR_GRAPH=0 runs
- * them eagerly). */
+ * them eagerly).  The Krylov vectors and the iterate live in the workspace in the
+ * transforms' tiled layout (each transform workgroup reads or writes one contiguous
+ * tile of traces); b is converted on entry and x written at the end
+ * (MDC_LSQR_TILED=0 keeps the [nt][n][nv] layout throughout, for comparison). */
 mdc_status lsqr_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x, double* hist,
                       void* work, size_t work_bytes, void* stream);
 
@@ -321,7 +324,8 @@ typedef struct {
 } serve_req;
 
 /* Arena bytes one request of nv points occupies on the full grid (an upper bound for lattice
- * levels, whose slots hold four vectors of 1/d the length instead of three full ones). */
+ * levels, whose four vectors have 1/d the length); the vectors are held in the transforms'
+ * tiled layout and the solution is written to x_out when the request finishes. */
 mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes);
 /* Arena bytes serve_create reserves for the lattice level of decimation 2 or 4 (index tables
  * and the gathered kernel in the op's storage format). */

@@ -210,9 +210,10 @@ struct Spectra {
 
 // pre: optional window [nr][nv] on the model side (a time-domain preconditioner P, so the
 // operator is C P, adjoint P C^H), or nullptr.  ws: spectra buffers replacing the op's workspace.
+// tiled: in and out in the tiled time layout of the solvers (fft_tile), else [nt][n][nv].
 mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjoint, hipStream_t st,
                        const int* pre = nullptr, const double* in_scale = nullptr, const Recur* rec = nullptr,
-                       const Spectra* ws = nullptr) {
+                       const Spectra* ws = nullptr, int tiled = 0) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded (mdc_set_kernel / mdc_synth_kernel)");
   if (nv < 1 || nv > (ws ? ws->d.max_cols : d.max_cols))
@@ -228,7 +229,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   float2* spec_out = adjoint ? sR : sS;
   {
     Stage t(op, 0, st);
-    FftSeg seg{in, adjoint ? nullptr : pre, 0, 0, in_scale};
+    FftSeg seg{in, adjoint ? nullptr : pre, 0, 0, in_scale, tiled};
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, nin, nv, nv, seg, spec_in, st)) != MDC_OK) return s;
   }
   {
@@ -240,6 +241,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
   {
     Stage t(op, 3, st);
     IfftSeg seg{out, nullptr, adjoint ? pre : nullptr, 0, 0, 1.0f};
+    seg.tiled = tiled;
     attach_recur(seg, rec, 0);
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, nout, nv, nv, seg, spec_out, st)) != MDC_OK) return s;
   }
@@ -249,7 +251,7 @@ mdc_status apply_plain(mdc_op* op, const float* in, float* out, int nv, int adjo
 // Marchenko block operator (Eq.5): one kernel pass with columns [block for R | conj block for R*].
 mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in0, const float* in1, float* out0,
                            float* out1, int adjoint, hipStream_t st, int mode = 0,
-                           const double* in_scale = nullptr, const Recur* rec = nullptr) {
+                           const double* in_scale = nullptr, const Recur* rec = nullptr, int tiled = 0) {
   const mdc_desc& d = op->d;
   if (!op->kernel_ready) return fail(MDC_EINVAL, "kernel not loaded");
   if (d.ns != d.nr) return fail(MDC_EINVAL, "Marchenko operator needs ns == nr (got %d, %d)", d.ns, d.nr);
@@ -267,8 +269,8 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     Stage t(op, 0, st);
     // forward: R acts on in1, R* on in0; adjoint: R^H on Theta in0, R*^H on Theta in1
     const int* pre = adjoint ? onset : nullptr;
-    FftSeg a{adjoint ? in0 : in1, pre, 0, 0, in_scale};
-    FftSeg b{adjoint ? in1 : in0, pre, 1, nv, in_scale};
+    FftSeg a{adjoint ? in0 : in1, pre, 0, 0, in_scale, tiled};
+    FftSeg b{adjoint ? in1 : in0, pre, 1, nv, in_scale, tiled};
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_in, st)) != MDC_OK) return s;
     if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, b, spec_in, st)) != MDC_OK) return s;
   }
@@ -285,6 +287,7 @@ mdc_status apply_marchenko(mdc_op* op, const int* onset, int nv, const float* in
     const float sg = mode == 1 ? 1.0f : -1.0f;
     IfftSeg a{adjoint ? out1 : out0, mode == 1 ? nullptr : (adjoint ? in1 : in0), post, 0, 0, sg, 1.0f, in_scale};
     IfftSeg b{adjoint ? out0 : out1, mode == 1 ? nullptr : (adjoint ? in0 : in1), post, 1, nv, sg, 1.0f, in_scale};
+    a.tiled = b.tiled = tiled;
     attach_recur(a, rec, 0);
     attach_recur(b, rec, irfft_blocks(d.nt, n, nv));
     if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, nv, N, a, spec_out, st)) != MDC_OK) return s;
@@ -530,12 +533,12 @@ mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
 
 // One application of the solver's operator (MDC or Marchenko) to in_scale * in (in_scale a
 // device scalar, or nullptr for 1); Marchenko vectors are two contiguous blocks of `half`
-// elements.
+// elements; tiled: vectors in the tiled time layout (fft_tile).
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st, const double* in_scale, const Recur* rec) {
+                    size_t half, hipStream_t st, const double* in_scale, const Recur* rec, int tiled) {
   if (kind == MDC_OP_MARCHENKO)
-    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st, 0, in_scale, rec);
-  return apply_plain(op, in, out, nv, adjoint, st, onset, in_scale, rec);
+    return apply_marchenko(op, onset, nv, in, in + half, out, out + half, adjoint, st, 0, in_scale, rec, tiled);
+  return apply_plain(op, in, out, nv, adjoint, st, onset, in_scale, rec, nullptr, tiled);
 }
 }  // namespace mdc
 

@@ -12,10 +12,11 @@
 // The product family of every apply is fixed at capture time, so the key also holds the
 // tuning-table generation and the forced-family switch.
 struct LsqrGraphKey {
-  int kind, nv, fused, tune_gen, forced;
+  int kind, nv, fused, tiled, tune_gen, forced;
   const void *onset, *work, *x, *hist, *b;
   bool operator==(const LsqrGraphKey& o) const {
-    return kind == o.kind && nv == o.nv && fused == o.fused && tune_gen == o.tune_gen && forced == o.forced &&
+    return kind == o.kind && nv == o.nv && fused == o.fused && tiled == o.tiled && tune_gen == o.tune_gen &&
+           forced == o.forced &&
            onset == o.onset && work == o.work && x == o.x && hist == o.hist && b == o.b;
   }
 };
@@ -86,6 +87,7 @@ struct FftSeg {
   int conj;            // conjugate the spectrum
   int c0;              // first spectral column
   const double* dscale = nullptr;  // optional device scalar multiplying the input as it is read
+  int tiled = 0;       // input in the tiled layout (fft_tile), else [nt][n][nv]
 };
 struct IfftSeg {
   float* out;          // time-domain output [nt][n][nv]
@@ -103,6 +105,7 @@ struct IfftSeg {
   const double* acc_c2 = nullptr;
   float acc_sgn = 0.f;
   double* part = nullptr;
+  int tiled = 0;       // out, ident in the tiled layout (fft_tile), else [nt][n][nv]
 };
 
 // Fused recurrence handed to an apply: out = op(in) + sgn * (*c1) * (*c2 or 1) * out (c1 may be
@@ -131,6 +134,19 @@ mdc_status irfft_launch(const float2* tw, int nt, int nfmax, int n, int nv, int 
                         const float2* spec, hipStream_t st);
 // Workgroups of one inverse launch over n * nv traces (slots of its partial sums).
 int irfft_blocks(int nt, int n, int nv);
+// Tiled time layout of the solvers' vectors: the Q traces in tiles of T = fft_tile(nt, Q)
+// consecutive traces (the transforms' workgroup width), tile j holding [nt][T] floats at
+// j * nt * T; the traces of the last tile past Q are padding and hold zeros.  A vector block
+// then takes tiled_len(nt, Q) floats, and every transform reads or writes whole tiles.
+int fft_tile(int nt, int Q);
+inline size_t tiled_len(int nt, int Q) {
+  const int T = fft_tile(nt, Q);
+  return (size_t)nt * ((size_t)(Q + T - 1) / T) * T;
+}
+// Between `blocks` consecutive blocks of [nt][Q] floats and their tiled form (tiled_len each):
+// to_tiles writes whole tiles (zero padding traces), from_tiles the [nt][Q] blocks.
+void launch_to_tiles(float* dst, const float* src, int nt, int Q, int blocks, hipStream_t st);
+void launch_from_tiles(float* dst, const float* src, int nt, int Q, int blocks, hipStream_t st);
 
 // Kernel product over all frequencies: forward Y_f = K_f X_f (ns x nr times nr x ncols),
 // adjoint X_f = K_f^H Y_f.  Spectra [nfmax][n][ncols].  The kernel family comes from the

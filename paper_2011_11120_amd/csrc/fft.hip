@@ -154,6 +154,13 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * q8 + min(xcd, rem) + (b >> 3);
 }
 
+// Element (t, q) of a time-domain array of Q traces: row-major [nt][Q], or tiled (solver
+// vectors): tiles of CB consecutive traces, each tile [nt][CB] contiguous.
+template <int CB, int NT>
+__device__ __forceinline__ size_t time_index(int t, int q, int Q, int tiled) {
+  return tiled ? (size_t)(q / CB) * (NT * CB) + (size_t)t * CB + (q % CB) : (size_t)t * Q + q;
+}
+
 
 // ----------------------------------------------------------------- forward ---
 // VEC: Q % 4 == 0 and x 16-byte aligned (four traces per 16-byte load);
@@ -164,7 +171,7 @@ template <int M, int CB, bool VEC, bool CONTIG, int NTH>
 __global__ __launch_bounds__(NTH) void rfft_trunc_kernel(
     const float* __restrict__ x, const int* __restrict__ onset, int conj, const float2* __restrict__ tw,
     int nfmax, int n, int nv, int ldc, int c0, float scale, float2* __restrict__ spec,
-    const double* __restrict__ dscale) {
+    const double* __restrict__ dscale, int tiled) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
   float2* lds = sh;            // [M][CB]
   float2* tws = sh + M * CB;   // [2M]
@@ -187,8 +194,8 @@ __global__ __launch_bounds__(NTH) void rfft_trunc_kernel(
       const int q = q0 + 4 * g;
       ra[i] = rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (task < TASKS && q < Q) {  // Q % 4 == 0: the whole group is in range
-        ra[i] = *reinterpret_cast<const float4*>(x + (size_t)(2 * m) * Q + q);
-        rb[i] = *reinterpret_cast<const float4*>(x + (size_t)(2 * m + 1) * Q + q);
+        ra[i] = *reinterpret_cast<const float4*>(x + time_index<CB, NT>(2 * m, q, Q, tiled));
+        rb[i] = *reinterpret_cast<const float4*>(x + time_index<CB, NT>(2 * m + 1, q, Q, tiled));
       }
     }
 #pragma unroll
@@ -224,8 +231,8 @@ __global__ __launch_bounds__(NTH) void rfft_trunc_kernel(
       const int m = tid / CB + i * ROWS;
       ra[i] = rb[i] = 0.f;
       if (m < M && qok) {
-        ra[i] = x[(size_t)(2 * m) * Q + q];
-        rb[i] = x[(size_t)(2 * m + 1) * Q + q];
+        ra[i] = x[time_index<CB, NT>(2 * m, q, Q, tiled)];
+        rb[i] = x[time_index<CB, NT>(2 * m + 1, q, Q, tiled)];
       }
     }
 #pragma unroll
@@ -285,7 +292,8 @@ __global__ __launch_bounds__(NTH) void irfft_pad_kernel(
     const float2* __restrict__ spec, int ldc, int c0, int conj, const float2* __restrict__ tw, int nfmax,
     int n, int nv, float scale, float* out, const float* ident,
     const int* __restrict__ onset, float sign, float iscale0, const double* __restrict__ ident_dscale,
-    const double* __restrict__ acc_c1, const double* __restrict__ acc_c2, float acc_sgn, double* __restrict__ part) {
+    const double* __restrict__ acc_c1, const double* __restrict__ acc_c2, float acc_sgn, double* __restrict__ part,
+    int tiled) {
   extern __shared__ __attribute__((aligned(16))) float2 sh[];
   __shared__ double red[NTH / 64];
   float2* lds = sh;
@@ -394,7 +402,7 @@ __global__ __launch_bounds__(NTH) void irfft_pad_kernel(
           if (!in_window(2 * m + 1, NT, on)) e1[h] = 0.f;
         }
       }
-      const size_t i0 = (size_t)(2 * m) * Q + q, i1 = (size_t)(2 * m + 1) * Q + q;
+      const size_t i0 = time_index<CB, NT>(2 * m, q, Q, tiled), i1 = time_index<CB, NT>(2 * m + 1, q, Q, tiled);
       float4 o0 = make_float4(e0[0], e0[1], e0[2], e0[3]);
       float4 o1 = make_float4(e1[0], e1[1], e1[2], e1[3]);
       if (ident != nullptr) {
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(NTH) void irfft_pad_kernel(
           const int t = 2 * m + h;
           float val = (h == 0 ? z.x : z.y) * scale * sign;
           if (!in_window(t, NT, on)) val = 0.f;
-          const size_t idx = (size_t)t * Q + q;
+          const size_t idx = time_index<CB, NT>(t, q, Q, tiled);
           if (ident != nullptr) val += iscale * ident[idx];
           if (acc) val += coef * out[idx];
           out[idx] = val;
@@ -481,7 +489,7 @@ mdc_status rfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const F
     attr = true;
   }
   hipLaunchKernelGGL((rfft_trunc_kernel<M, CB, VEC, CONTIG, NTH>), dim3((Q + CB - 1) / CB), dim3(NTH), lds, st, s.in,
-                     s.onset, s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec, s.dscale);
+                     s.onset, s.conj, tw, nfmax, n, nv, ldc, s.c0, scale, spec, s.dscale, s.tiled);
   return check_launch("rfft_trunc_kernel");
 }
 
@@ -521,7 +529,7 @@ mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const 
   }
   hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG, NTH>), dim3((Q + CB - 1) / CB), dim3(NTH), lds, st, spec,
                      ldc, s.c0, s.conj, tw, nfmax, n, nv, scale, s.out, s.ident, s.onset, s.sign, s.ident_scale,
-                     s.ident_dscale, s.acc_c1, s.acc_c2, s.acc_sgn, s.part);
+                     s.ident_dscale, s.acc_c1, s.acc_c2, s.acc_sgn, s.part, s.tiled);
   return check_launch("irfft_pad_kernel");
 }
 
@@ -566,6 +574,20 @@ int irfft_blocks(int nt, int n, int nv) {
     case 512: return irfft_blocks_m<256>(Q);
     case 1024: return irfft_blocks_m<512>(Q);
     case 2048: return irfft_blocks_m<1024>(Q);
+    default: return 0;
+  }
+}
+
+int fft_tile(int nt, int Q) {
+  switch (nt) {
+    case 16: return pick_cb<8, false>(Q);
+    case 32: return pick_cb<16, false>(Q);
+    case 64: return pick_cb<32, false>(Q);
+    case 128: return pick_cb<64, false>(Q);
+    case 256: return pick_cb<128, false>(Q);
+    case 512: return pick_cb<256, false>(Q);
+    case 1024: return pick_cb<512, false>(Q);
+    case 2048: return pick_cb<1024, false>(Q);
     default: return 0;
   }
 }

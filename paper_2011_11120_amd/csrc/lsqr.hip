@@ -19,7 +19,8 @@
 namespace mdc {
 
 mdc_status apply_op(mdc_op* op, int kind, const int* onset, int nv, int adjoint, const float* in, float* out,
-                    size_t half, hipStream_t st, const double* in_scale = nullptr, const Recur* rec = nullptr);
+                    size_t half, hipStream_t st, const double* in_scale = nullptr, const Recur* rec = nullptr,
+                    int tiled = 0);
 
 namespace {
 
@@ -265,21 +266,32 @@ void lsqr_after_adj_fused(const LsqrState& s, hipStream_t st) {
 namespace {
 
 struct Sizes {
-  size_t model, data;  // element counts
+  size_t model, data;        // element counts
+  int qm, qd;                // traces per block of a model / data vector
+  size_t bm, bd;             // elements per block (tiled: whole tiles)
+  int blocks;                // blocks per vector (2 for the Marchenko system)
   int parts_fwd, parts_adj;  // partial-sum slots of the fused recurrences
 };
 
-Sizes sizes_of(const mdc_desc& d, const lsqr_desc& ld) {
+// tiled: vectors in the transforms' tiled time layout (whole tiles, zero padding traces).
+Sizes sizes_of(const mdc_desc& d, const lsqr_desc& ld, bool tiled) {
   Sizes z{};
+  auto blk = [&](int q) { return tiled ? tiled_len(d.nt, q) : (size_t)d.nt * q; };
   if (ld.kind == MDC_OP_MARCHENKO) {
-    z.model = z.data = 2ull * d.nt * d.ns * ld.nv;
+    z.qm = z.qd = d.ns * ld.nv;
+    z.blocks = 2;
     z.parts_fwd = z.parts_adj = 2 * irfft_blocks(d.nt, d.ns, ld.nv);
   } else {
-    z.model = (size_t)d.nt * d.nr * ld.nv;
-    z.data = (size_t)d.nt * d.ns * ld.nv;
+    z.qm = d.nr * ld.nv;
+    z.qd = d.ns * ld.nv;
+    z.blocks = 1;
     z.parts_fwd = irfft_blocks(d.nt, d.ns, ld.nv);
     z.parts_adj = irfft_blocks(d.nt, d.nr, ld.nv);
   }
+  z.bm = blk(z.qm);
+  z.bd = blk(z.qd);
+  z.model = z.blocks * z.bm;
+  z.data = z.blocks * z.bd;
   return z;
 }
 
@@ -287,11 +299,13 @@ size_t parts_bytes_of(const Sizes& z) {
   return align_up((size_t)(z.parts_fwd > z.parts_adj ? z.parts_fwd : z.parts_adj) * sizeof(double), 256);
 }
 
+// Sized for the tiled layout (never smaller than the plain one) plus the solution in that layout.
 size_t work_bytes_of(const Sizes& z) {
   size_t b = lsqr_scalars_bytes();
   b += 2 * align_up(z.data * 4, 256);   // u, t
   b += 3 * align_up(z.model * 4, 256);  // v, w, t2
   b += parts_bytes_of(z);               // partial sums of the fused recurrences
+  b += align_up(z.model * 4, 256);      // x in the tiled layout (copied to the caller's x at the end)
   return b;
 }
 
@@ -311,7 +325,7 @@ mdc_status lsqr_check(const mdc_op* op, const mdc_desc& d, const lsqr_desc* ld) 
   return MDC_OK;
 }
 
-size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld) { return work_bytes_of(sizes_of(d, ld)); }
+size_t lsqr_work_bytes(const mdc_desc& d, const lsqr_desc& ld) { return work_bytes_of(sizes_of(d, ld, true)); }
 
 __global__ void zero_vec(float* __restrict__ x, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] = 0.f;
@@ -322,40 +336,93 @@ __global__ void copy_f32(float* __restrict__ dst, const float* __restrict__ src,
     dst[i] = src[i];
 }
 
+// Block b of a vector between the caller's layout [nt][Q] and the tiled layout (tiles of T
+// traces, [nt][T] each, tile_len = nt * T): to_tiles writes every element of the tiled block,
+// zeros on the padding traces; from_tiles writes the caller's block.
+__global__ void to_tiles(float* __restrict__ dst, const float* __restrict__ src, int nt, int Q, int T,
+                         size_t blk_tiled, size_t blk_plain, int blocks) {
+  const size_t tile_len = (size_t)nt * T, total = blk_tiled * blocks;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / blk_tiled, e = i - b * blk_tiled;
+    const size_t j = e / tile_len, r = e - j * tile_len;
+    const int t = (int)(r / T), q = (int)(j * T + (r - (size_t)t * T));
+    dst[i] = q < Q ? src[b * blk_plain + (size_t)t * Q + q] : 0.f;
+  }
+}
+__global__ void from_tiles(float* __restrict__ dst, const float* __restrict__ src, int nt, int Q, int T,
+                           size_t blk_tiled, size_t blk_plain, int blocks) {
+  const size_t total = blk_plain * blocks;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / blk_plain, e = i - b * blk_plain;
+    const int t = (int)(e / Q), q = (int)(e - (size_t)t * Q);
+    dst[i] = src[b * blk_tiled + (size_t)(q / T) * nt * T + (size_t)t * T + (q % T)];
+  }
+}
+
+void launch_to_tiles(float* dst, const float* src, int nt, int Q, int blocks, hipStream_t st) {
+  const size_t blk = tiled_len(nt, Q);
+  hipLaunchKernelGGL(to_tiles, dim3(grid_for(blk * blocks)), dim3(kThreads), 0, st, dst, src, nt, Q, fft_tile(nt, Q),
+                     blk, (size_t)nt * Q, blocks);
+}
+void launch_from_tiles(float* dst, const float* src, int nt, int Q, int blocks, hipStream_t st) {
+  const size_t blk = tiled_len(nt, Q);
+  hipLaunchKernelGGL(from_tiles, dim3(grid_for((size_t)nt * Q * blocks)), dim3(kThreads), 0, st, dst, src, nt, Q,
+                     fft_tile(nt, Q), blk, (size_t)nt * Q, blocks);
+}
+
 mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
                     void* work, hipStream_t st) {
-  const Sizes z = sizes_of(d, ld);
+  // Krylov vectors in the transforms' tiled layout (each transform workgroup reads or writes one
+  // contiguous tile); MDC_LSQR_TILED=0 keeps the caller's [nt][n][nv] layout throughout.
+  const char* tl = getenv("MDC_LSQR_TILED");
+  const int tiled = (tl && tl[0] == '0') ? 0 : 1;
+  const Sizes z = sizes_of(d, ld, tiled != 0);
+  const Sizes zt = sizes_of(d, ld, true);  // the workspace layout (lsqr_work_bytes)
   char* p = static_cast<char*>(work);
   LsqrState S{};
   S.sc = p;
   p += lsqr_scalars_bytes();
-  S.u = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
-  S.t = reinterpret_cast<float*>(p); p += align_up(z.data * 4, 256);
-  S.v = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
-  S.w = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
-  S.t2 = reinterpret_cast<float*>(p); p += align_up(z.model * 4, 256);
+  S.u = reinterpret_cast<float*>(p); p += align_up(zt.data * 4, 256);
+  S.t = reinterpret_cast<float*>(p); p += align_up(zt.data * 4, 256);
+  S.v = reinterpret_cast<float*>(p); p += align_up(zt.model * 4, 256);
+  S.w = reinterpret_cast<float*>(p); p += align_up(zt.model * 4, 256);
+  S.t2 = reinterpret_cast<float*>(p); p += align_up(zt.model * 4, 256);
   const char* f = getenv("MDC_LSQR_FUSE");
   if (!(f && f[0] == '0')) {
     S.rpart = reinterpret_cast<double*>(p);
     S.nparts_fwd = z.parts_fwd;
     S.nparts_adj = z.parts_adj;
   }
-  S.x = x;
+  p += parts_bytes_of(zt);
+  S.x = tiled ? reinterpret_cast<float*>(p) : x;
   S.hist = hist;
   S.model = z.model;
   S.data = z.data;
   const int kind = ld.kind;
-  const size_t half = z.model / 2;  // Marchenko block size (model == data)
+  const size_t half = z.bm;  // Marchenko block size (model == data)
   mdc_status s;
 
-  hipLaunchKernelGGL(copy_f32, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.u, b, z.data);
+  if (tiled) {
+    // u = b in tiles; the transforms write only the traces of a vector, so the padding traces
+    // of every vector they write start at zero (the recurrences keep them there)
+    launch_to_tiles(S.u, b, d.nt, z.qd, z.blocks, st);
+    hipLaunchKernelGGL(zero_vec, dim3(grid_for(z.model)), dim3(kThreads), 0, st, S.v, z.model);
+    if (!S.rpart) {  // the separate-pass recurrences read the transforms' outputs t and t2 whole
+      hipLaunchKernelGGL(zero_vec, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.t, z.data);
+      hipLaunchKernelGGL(zero_vec, dim3(grid_for(z.model)), dim3(kThreads), 0, st, S.t2, z.model);
+    }
+  } else {
+    hipLaunchKernelGGL(copy_f32, dim3(grid_for(z.data)), dim3(kThreads), 0, st, S.u, b, z.data);
+  }
   lsqr_after_b(S, st);
   if (S.rpart) {
     const Recur ri = lsqr_recur_init(S);
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, st, lsqr_uinv(S), &ri)) != MDC_OK) return s;
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, st, lsqr_uinv(S), &ri, tiled)) != MDC_OK)
+      return s;
     lsqr_after_init_adj_fused(S, st);
   } else {
-    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st, lsqr_uinv(S))) != MDC_OK) return s;
+    if ((s = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, st, lsqr_uinv(S), nullptr, tiled)) != MDC_OK)
+      return s;
     lsqr_after_init_adj(S, st);
   }
   if ((s = check_launch("lsqr init")) != MDC_OK) return s;
@@ -363,31 +430,41 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
     mdc_status e;
     if (S.rpart) {
       const Recur rf = lsqr_recur_fwd(S);
-      if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.u, half, q, lsqr_vinv(S), &rf)) != MDC_OK) return e;
+      if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.u, half, q, lsqr_vinv(S), &rf, tiled)) != MDC_OK)
+        return e;
       lsqr_after_fwd_fused(S, q);
       const Recur ra = lsqr_recur_adj(S);
-      if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, q, lsqr_uinv(S), &ra)) != MDC_OK) return e;
+      if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.v, half, q, lsqr_uinv(S), &ra, tiled)) != MDC_OK)
+        return e;
       lsqr_after_adj_fused(S, q);
       return check_launch("lsqr iteration");
     }
-    if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q, lsqr_vinv(S))) != MDC_OK) return e;
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 0, S.v, S.t, half, q, lsqr_vinv(S), nullptr, tiled)) != MDC_OK)
+      return e;
     lsqr_after_fwd(S, q);
-    if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q, lsqr_uinv(S))) != MDC_OK) return e;
+    if ((e = apply_op(op, kind, ld.onset, ld.nv, 1, S.u, S.t2, half, q, lsqr_uinv(S), nullptr, tiled)) != MDC_OK)
+      return e;
     lsqr_after_adj(S, q);
     return check_launch("lsqr iteration");
   };
+  // the solution in the caller's layout (after the last iteration on the stream)
+  auto finish = [&]() -> mdc_status {
+    if (!tiled) return MDC_OK;
+    launch_from_tiles(x, S.x, d.nt, z.qm, z.blocks, st);
+    return check_launch("lsqr solution");
+  };
   if (ld.niter >= 1 && (s = iteration(st)) != MDC_OK) return s;  // eager: every kernel variant initialised
-  if (ld.niter < 2) return MDC_OK;
+  if (ld.niter < 2) return finish();
   const char* g = getenv("MDC_LSQR_GRAPH");
   const bool use_graph = !op->prof && !(g && g[0] == '0');
   if (!use_graph) {
     for (int it = 2; it <= ld.niter; ++it)
       if ((s = iteration(st)) != MDC_OK) return s;
-    return MDC_OK;
+    return finish();
   }
   // Capture one iteration (identical launches every time: the iteration counter lives on the
   // device) on the op's private stream, then replay it on the caller's stream.
-  const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, op->tune_gen, forced_family(op), ld.onset, work, x, hist, b};
+  const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, tiled, op->tune_gen, forced_family(op), ld.onset, work, x, hist, b};
   if (!op->lsqr_exec || !(op->lsqr_key == key)) {
     if (op->lsqr_exec) {
       hipGraphExecDestroy(op->lsqr_exec);
@@ -415,14 +492,14 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   }
   for (int it = 2; it <= ld.niter; ++it)
     if (hipGraphLaunch(op->lsqr_exec, st) != hipSuccess) return fail(MDC_EDEVICE, "hipGraphLaunch failed");
-  return MDC_OK;
+  return finish();
 }
 
 // CGLS (the paper's solver): conjugate gradients on the normal equations, x0 = 0, fixed niter.
 // Vectors FP32 (r, q data-sized; s, p model-sized); gamma, alpha, beta and the norms FP64.
 mdc_status cgls_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const float* b, float* x, double* hist,
                     void* work, hipStream_t st) {
-  const Sizes z = sizes_of(d, ld);
+  const Sizes z = sizes_of(d, ld, false);  // the caller's layout (within the workspace sized for tiles)
   char* w = static_cast<char*>(work);
   Scalars* sc = reinterpret_cast<Scalars*>(w);
   w += lsqr_scalars_bytes();

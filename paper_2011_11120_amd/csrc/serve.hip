@@ -63,18 +63,25 @@ __device__ __forceinline__ bool lattice_keep(int r, int nx, int d) {
 }
 
 // Trace i of the request's problem is full-grid trace idx[i] (a lattice level) or i (the full
-// grid, n = nx^2, traces off the lattice of d masked out).
-// onset[i][v] = max(rint(td/dt) - eps, 0) on kept traces, 0 elsewhere; keep[i][v] = nt or 0;
-// fd[t][i][v] = ricker(lag(t) dt + td) on kept traces, 0 elsewhere; td = |x_r - x_v| / c (FP64,
-// no contraction, so the integer onsets match a host computation exactly).
+// grid, n = nx^2, traces off the lattice of d masked out); trace q = i nv + v.
+// onset[q] = max(rint(td/dt) - eps, 0) on kept traces, 0 elsewhere; keep[q] = nt or 0;
+// fd(t, q) = ricker(lag(t) dt + td) on kept traces, 0 elsewhere, written in the tiled layout
+// (tiles of T traces, zero padding traces); td = |x_r - x_v| / c (FP64, no contraction, so the
+// integer onsets match a host computation exactly).
 __global__ __launch_bounds__(kThreads) void request_inputs(int nt, int nx, double dx, double dt, double c, int eps,
                                                            double fp, int d, int n, const int* __restrict__ idx,
-                                                           int nv, PointArgs P, int* __restrict__ onset,
+                                                           int nv, PointArgs P, int T, int* __restrict__ onset,
                                                            int* __restrict__ keep, float* __restrict__ fd) {
-  const size_t Q = (size_t)n * nv;
-  for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < (size_t)nt * Q; e += (size_t)gridDim.x * kThreads) {
-    const int t = (int)(e / Q);
-    const size_t q = e - (size_t)t * Q;
+  const size_t Q = (size_t)n * nv, tile = (size_t)nt * T;
+  const size_t total = (Q + T - 1) / T * tile;
+  for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < total; e += (size_t)gridDim.x * kThreads) {
+    const size_t j = e / tile, rr = e - j * tile;
+    const int t = (int)(rr / T);
+    const size_t q = j * T + (rr - (size_t)t * T);
+    if (q >= Q) {
+      fd[e] = 0.f;
+      continue;
+    }
     const int i = (int)(q / nv), v = (int)(q - (size_t)i * nv);
     const int r = idx ? idx[i] : i;
     const bool kept = idx ? true : lattice_keep(r, nx, d);
@@ -103,18 +110,21 @@ __global__ void zero_f32(float* __restrict__ p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
-// out[b][t][r][v] = x[b][t][pos[r]][v] where the full-grid trace r is on the lattice (pos[r] >= 0),
-// 0 elsewhere: a lattice solution [2][nt][nsub][nv] written onto the full grid [2][nt][n][nv].
+// out[b][t][r][v] = x_b(t, pos[r] nv + v) where the full-grid trace r is on the lattice
+// (pos[r] >= 0), 0 elsewhere: a lattice solution (two blocks of blk floats in the tiled layout,
+// tiles of T traces) written onto the full grid [2][nt][n][nv].
 __global__ __launch_bounds__(kThreads) void scatter_lattice(const float* __restrict__ x, float* __restrict__ out,
-                                                            const int* __restrict__ pos, int nt, int n, int nsub,
-                                                            int nv) {
+                                                            const int* __restrict__ pos, int nt, int n, int nv,
+                                                            int T, size_t blk) {
   const size_t total = 2ull * nt * n * nv;
   for (size_t e = blockIdx.x * (size_t)kThreads + threadIdx.x; e < total; e += (size_t)gridDim.x * kThreads) {
     const size_t bt = e / ((size_t)n * nv);  // block * nt + t
     const size_t q = e - bt * (size_t)n * nv;
     const int r = (int)(q / nv), v = (int)(q - (size_t)r * nv);
+    const int b = (int)(bt / nt), t = (int)(bt - (size_t)b * nt);
     const int p = pos[r];
-    out[e] = p >= 0 ? x[(bt * nsub + p) * nv + v] : 0.f;
+    const size_t qs = (size_t)p * nv + v;  // lattice trace
+    out[e] = p >= 0 ? x[b * blk + qs / T * ((size_t)nt * T) + (size_t)t * T + qs % T] : 0.f;
   }
 }
 
@@ -155,15 +165,15 @@ struct Request {
 // Partial-sum slots of one request's fused recurrences (two inverse segments per apply).
 int parts_for(int nt, int n, int nv) { return 2 * irfft_blocks(nt, n, nv); }
 
-// Arena bytes of a request on n traces: onsets, keep mask, scalars, partial sums, the Krylov
-// vectors u, v, w (recurrences fused into the applies) and, on a lattice level, its own
-// solution x (scattered onto the caller's full-grid output at the end).
-size_t slot_bytes_for(int nt, int n, int nv, bool lattice) {
-  const size_t vec = 2ull * nt * n * nv * 4;  // two Marchenko blocks
+// Arena bytes of a request on n traces: onsets, keep mask, scalars, partial sums, and the
+// vectors u, v, w (recurrences fused into the applies) and x, all in the transforms' tiled
+// layout (x is written onto the caller's output, [2][nt][nx^2][nv], when the request finishes).
+size_t slot_bytes_for(int nt, int n, int nv) {
+  const size_t vec = 2 * tiled_len(nt, n * nv) * 4;  // two Marchenko blocks
   size_t b = 2 * align_up((size_t)n * nv * 4, 256);
   b += lsqr_scalars_bytes();
   b += align_up((size_t)parts_for(nt, n, nv) * sizeof(double), 256);
-  b += (lattice ? 4 : 3) * align_up(vec, 256);
+  b += 4 * align_up(vec, 256);
   return b;
 }
 
@@ -281,28 +291,29 @@ mdc_status enqueue_level(mdc_server* S, const Level& L, std::vector<Request*>& p
   float2* spec_out = fwd ? op->specS : op->specR;
   mdc_status s;
   for (Request* r : part) {
-    const size_t half = (size_t)d.nt * n * r->nv;
+    const size_t half = tiled_len(d.nt, n * r->nv);  // one block of a request vector (tiled layout)
     if (r->phase == kData) {
-      FftSeg a{r->S.w, nullptr, 0, r->c0};  // fd was generated into w (block 0)
+      FftSeg a{r->S.w, nullptr, 0, r->c0, nullptr, 1};  // fd was generated into w (block 0)
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
     } else if (fwd) {  // R on v1, R* on v0 (stored v times 1/alpha)
-      FftSeg a{r->S.v + half, nullptr, 0, r->c0, lsqr_vinv(r->S)};
-      FftSeg b{r->S.v, nullptr, 1, r->c0 + r->nv, lsqr_vinv(r->S)};
+      FftSeg a{r->S.v + half, nullptr, 0, r->c0, lsqr_vinv(r->S), 1};
+      FftSeg b{r->S.v, nullptr, 1, r->c0 + r->nv, lsqr_vinv(r->S), 1};
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
     } else {  // R^H on Theta u0, R*^H on Theta u1 (stored u times 1/beta)
-      FftSeg a{r->S.u, r->onset, 0, r->c0, lsqr_uinv(r->S)};
-      FftSeg b{r->S.u + half, r->onset, 1, r->c0 + r->nv, lsqr_uinv(r->S)};
+      FftSeg a{r->S.u, r->onset, 0, r->c0, lsqr_uinv(r->S), 1};
+      FftSeg b{r->S.u + half, r->onset, 1, r->c0 + r->nv, lsqr_uinv(r->S), 1};
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_in, st)) != MDC_OK) return s;
       if ((s = rfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, b, spec_in, st)) != MDC_OK) return s;
     }
   }
   if ((s = product_launch(op, fwd ? 0 : 1, spec_in, spec_out, N, st)) != MDC_OK) return s;
   for (Request* r : part) {
-    const size_t half = (size_t)d.nt * n * r->nv;
+    const size_t half = tiled_len(d.nt, n * r->nv);
     const float dsc = (float)r->decim;
     if (r->phase == kData) {  // u0 = d Theta R fd, u1 = 0 ; then beta u = b
       IfftSeg a{r->S.u, nullptr, r->onset, 0, r->c0, dsc};
+      a.tiled = 1;
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
       hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, st, r->S.u + half, half);
       lsqr_after_b(r->S, st);
@@ -310,6 +321,7 @@ mdc_status enqueue_level(mdc_server* S, const Level& L, std::vector<Request*>& p
       const Recur rec = lsqr_recur_fwd(r->S);
       IfftSeg a{r->S.u, r->S.v, r->onset, 0, r->c0, -dsc, 1.0f, lsqr_vinv(r->S)};
       IfftSeg b{r->S.u + half, r->S.v + half, r->onset, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_vinv(r->S)};
+      a.tiled = b.tiled = 1;
       attach_recur(a, &rec, 0);
       attach_recur(b, &rec, r->S.nparts_fwd / 2);
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
@@ -320,6 +332,7 @@ mdc_status enqueue_level(mdc_server* S, const Level& L, std::vector<Request*>& p
       const Recur rec = r->phase == kInitAdj ? lsqr_recur_init(r->S) : lsqr_recur_adj(r->S);
       IfftSeg a{r->S.v + half, r->S.u + half, km, 0, r->c0, -dsc, 1.0f, lsqr_uinv(r->S)};
       IfftSeg b{r->S.v, r->S.u, km, 1, r->c0 + r->nv, -dsc, 1.0f, lsqr_uinv(r->S)};
+      a.tiled = b.tiled = 1;
       attach_recur(a, &rec, 0);
       attach_recur(b, &rec, r->S.nparts_adj / 2);
       if ((s = irfft_launch(op->tw, d.nt, d.nfmax, n, r->nv, N, a, spec_out, st)) != MDC_OK) return s;
@@ -413,9 +426,7 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
   return s;
 }
 
-size_t request_bytes(const mdc_server* S, const Request* r) {
-  return slot_bytes_for(S->op->d.nt, r->n, r->nv, r->lv != 0);
-}
+size_t request_bytes(const mdc_server* S, const Request* r) { return slot_bytes_for(S->op->d.nt, r->n, r->nv); }
 
 // Give a request its arena slot and generate its inputs (called with the lock held).
 bool admit(mdc_server* S, Request* r) {
@@ -427,7 +438,7 @@ bool admit(mdc_server* S, Request* r) {
   r->slot_bytes = bytes;
   char* p = S->arena_base + off;
   const int n = r->n;
-  const size_t vec = 2ull * d.nt * n * r->nv;
+  const size_t vec = 2 * tiled_len(d.nt, n * r->nv);
   r->onset = reinterpret_cast<int*>(p); p += align_up((size_t)n * r->nv * 4, 256);
   r->keep = reinterpret_cast<int*>(p); p += align_up((size_t)n * r->nv * 4, 256);
   r->S.sc = p; p += lsqr_scalars_bytes();
@@ -437,22 +448,30 @@ bool admit(mdc_server* S, Request* r) {
   r->S.v = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
   r->S.w = reinterpret_cast<float*>(p); p += align_up(vec * 4, 256);
   r->S.t = r->S.t2 = nullptr;
-  r->S.x = r->lv != 0 ? reinterpret_cast<float*>(p) : r->x_out;
+  r->S.x = reinterpret_cast<float*>(p);
   r->S.hist = r->hist;
   r->S.model = r->S.data = vec;
+  // the transforms write only the traces of u and v: their padding traces start at zero
+  hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, S->stream, r->S.u, vec);
+  hipLaunchKernelGGL(zero_f32, dim3(1024), dim3(kThreads), 0, S->stream, r->S.v, vec);
   hipLaunchKernelGGL(request_inputs, dim3(2048), dim3(kThreads), 0, S->stream, d.nt, S->g.nx, S->g.dx, S->g.dt,
-                     S->g.c, S->g.eps, S->g.fp, r->decim, n, (const int*)S->lv[r->lv].idx, r->nv, r->pts, r->onset,
-                     r->keep, r->S.w);
+                     S->g.c, S->g.eps, S->g.fp, r->decim, n, (const int*)S->lv[r->lv].idx, r->nv, r->pts,
+                     fft_tile(d.nt, n * r->nv), r->onset, r->keep, r->S.w);
   r->phase = kData;
   return true;
 }
 
-// A finished lattice-level request's solution onto the caller's full-grid output.
+// A finished request's solution (tiled, on its level's traces) onto the caller's full-grid output.
 void finish_output(mdc_server* S, const Request* r) {
-  if (r->lv == 0) return;
+  const int nt = S->op->d.nt;
+  if (r->lv == 0) {
+    launch_from_tiles(r->x_out, r->S.x, nt, r->n * r->nv, 2, S->stream);
+    return;
+  }
   const Level& L = S->lv[r->lv];
   hipLaunchKernelGGL(scatter_lattice, dim3(2048), dim3(kThreads), 0, S->stream, (const float*)r->S.x, r->x_out,
-                     (const int*)L.pos, S->op->d.nt, S->op->d.ns, L.n, r->nv);
+                     (const int*)L.pos, nt, S->op->d.ns, r->nv, fft_tile(nt, L.n * r->nv),
+                     tiled_len(nt, L.n * r->nv));
 }
 
 void release(mdc_server* S, Request* r) {
@@ -606,7 +625,7 @@ extern "C" {
 mdc_status serve_request_bytes(const mdc_op* op, int nv, size_t* bytes) {
   if (!op || !bytes) return fail(MDC_EINVAL, "NULL argument");
   if (nv < 1 || nv > kMaxPoints) return fail(MDC_EINVAL, "nv=%d outside [1, %d]", nv, kMaxPoints);
-  *bytes = slot_bytes_for(op->d.nt, op->d.ns, nv, false);
+  *bytes = slot_bytes_for(op->d.nt, op->d.ns, nv);
   return MDC_OK;
 }
 

@@ -154,6 +154,48 @@ def test_fused_norms_match_separate_passes_and_oracle(mdcmod, monkeypatch, case,
     kind, nt, nfmax, ns, nr, nv = case
     print(f"fused {solver} {case}", flush=True)
     niter = 6
+    op, b, args, A, AH, bl = solver_case(mdcmod, case)
+    run = op.lsqr if solver == "lsqr" else op.cgls
+    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
+    xf, hf = run(dev(b), niter, **args)
+    xf, hf = host(xf), host(hf)
+    monkeypatch.setenv("MDC_LSQR_FUSE", "0")
+    xs, hs = run(dev(b), niter, **args)
+    xs, hs = host(xs), host(hs)
+    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
+    assert rel2(xf, xs) < 1e-6
+    assert np.max(np.abs(hf - hs)) / hs[0] < 1e-6
+    xr, hr = (ol.lsqr if solver == "lsqr" else ol.cgls)(A, AH, bl, niter)
+    assert rel2(xf, np.stack(xr) if kind == "marchenko" else xr[0]) < TOL
+    assert np.max(np.abs(hf - hr) / hr[0]) < TOL
+
+
+@pytest.mark.parametrize("fuse", ["1", "0"])
+@pytest.mark.parametrize("case", FUSED_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_tiled_vectors_match_plain_layout(mdcmod, monkeypatch, case, fuse):
+    """LSQR keeps its Krylov vectors in the transforms' tiled layout (tiles of whole trace groups,
+    zero padding traces, converted at the boundary); the caller's layout (MDC_LSQR_TILED=0) gives
+    the same solution and residual history (the same per-element arithmetic; only the vector norms
+    outside the transforms are summed in another order), for odd and padded trace counts."""
+    print(f"tiled {case} fuse={fuse}", flush=True)
+    niter = 6
+    op, b, args, _, _, _ = solver_case(mdcmod, case)
+    monkeypatch.setenv("MDC_LSQR_FUSE", fuse)
+    monkeypatch.delenv("MDC_LSQR_TILED", raising=False)
+    xt, ht = op.lsqr(dev(b), niter, **args)
+    xt, ht = host(xt), host(ht)
+    monkeypatch.setenv("MDC_LSQR_TILED", "0")
+    xp, hp = op.lsqr(dev(b), niter, **args)
+    xp, hp = host(xp), host(hp)
+    monkeypatch.delenv("MDC_LSQR_TILED", raising=False)
+    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
+    assert rel2(xt, xp) < 1e-6
+    assert np.max(np.abs(ht - hp)) / hp[0] < 1e-6
+
+
+def solver_case(mdcmod, case):
+    """Operator, right-hand side, solver arguments and oracle operator of one FUSED_CASES entry."""
+    kind, nt, nfmax, ns, nr, nv = case
     if kind == "mdc":
         K = synth.random_complex_kernel(nfmax, ns, nr, seed=11)
         K *= 0.8 / max(power.spectral_norm(K[f], iters=40) for f in range(nfmax))
@@ -173,16 +215,4 @@ def test_fused_norms_match_separate_passes_and_oracle(mdcmod, monkeypatch, case,
         A = lambda v: list(omc.forward(K, onset, *v))
         AH = lambda u: list(omc.adjoint(K, onset, *u))
         bl = [d0, d1]
-    run = op.lsqr if solver == "lsqr" else op.cgls
-    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
-    xf, hf = run(dev(b), niter, **args)
-    xf, hf = host(xf), host(hf)
-    monkeypatch.setenv("MDC_LSQR_FUSE", "0")
-    xs, hs = run(dev(b), niter, **args)
-    xs, hs = host(xs), host(hs)
-    monkeypatch.delenv("MDC_LSQR_FUSE", raising=False)
-    assert rel2(xf, xs) < 1e-6
-    assert np.max(np.abs(hf - hs)) / hs[0] < 1e-6
-    xr, hr = (ol.lsqr if solver == "lsqr" else ol.cgls)(A, AH, bl, niter)
-    assert rel2(xf, np.stack(xr) if kind == "marchenko" else xr[0]) < TOL
-    assert np.max(np.abs(hf - hr) / hr[0]) < TOL
+    return op, b, args, A, AH, bl
