@@ -15,7 +15,9 @@
 // Layout: each workgroup owns CB consecutive traces (consecutive (n, v)
 // columns of the [nt][n][nv] array), so every global access of a time row or
 // a spectral row is contiguous across lanes; with 16-byte vectors a thread
-// moves four traces of one time row.  Long transforms with wide tiles run one
+// moves four traces of one time row.  The solvers' vectors may instead be
+// tiled (fft_tile): the workgroup's CB traces then form one contiguous
+// [nt][CB] tile, and its time-domain reads and writes one contiguous block.  Long transforms with wide tiles run one
 // wave per trace of the tile.  All global loads of a thread are issued
 // before any is consumed.  LDS holds z as [M][CB] complex plus the twiddle
 // table tw[k] = exp(-2 pi i k / nt) (built in FP64, rounded once to FP32).
@@ -588,7 +590,7 @@ int fft_tile(int nt, int Q) {
     case 512: return pick_cb<256, false>(Q);
     case 1024: return pick_cb<512, false>(Q);
     case 2048: return pick_cb<1024, false>(Q);
-    default: return 0;
+    default: return 4;  // not a supported length (the transforms refuse it)
   }
 }
 
