@@ -170,8 +170,13 @@ def test_fused_norms_match_separate_passes_and_oracle(mdcmod, monkeypatch, case,
     assert np.max(np.abs(hf - hr) / hr[0]) < TOL
 
 
+# 2209 traces x 4 points = 8836 traces per block: 16-trace tiles with a partly filled last tile on the
+# 16-byte path (the cases above pad only on the narrow-tile and scalar paths)
+TILED_PAD_CASES = [("mdc", 64, 10, 2209, 2209, 4), ("marchenko", 64, 10, 2209, 2209, 4)]
+
+
 @pytest.mark.parametrize("fuse", ["1", "0"])
-@pytest.mark.parametrize("case", FUSED_CASES, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("case", FUSED_CASES + TILED_PAD_CASES, ids=lambda c: "-".join(map(str, c)))
 def test_tiled_vectors_match_plain_layout(mdcmod, monkeypatch, case, fuse):
     """LSQR keeps its Krylov vectors in the transforms' tiled layout (tiles of whole trace groups,
     zero padding traces, converted at the boundary); the caller's layout (MDC_LSQR_TILED=0) gives
