@@ -198,6 +198,27 @@ def test_tiled_vectors_match_plain_layout(mdcmod, monkeypatch, case, fuse):
     assert np.max(np.abs(ht - hp)) / hp[0] < 1e-6
 
 
+@pytest.mark.parametrize("niter", [0, 1, 2])
+def test_tiled_short_solves(mdcmod, monkeypatch, niter):
+    """Solves that end before the captured iteration graph (0, 1 iterations) or right after its
+    first replay still write their tiled iterate back: x = 0 and phibar_0 = ||b|| after none, and
+    the caller's-layout run equals the tiled one after one or two."""
+    op, b, args, _, _, _ = solver_case(mdcmod, ("marchenko", 64, 25, 25, 25, 3))
+    monkeypatch.delenv("MDC_LSQR_TILED", raising=False)
+    xt, ht = op.lsqr(dev(b), niter, **args)
+    xt, ht = host(xt), host(ht)
+    monkeypatch.setenv("MDC_LSQR_TILED", "0")
+    xp, hp = op.lsqr(dev(b), niter, **args)
+    xp, hp = host(xp), host(hp)
+    monkeypatch.delenv("MDC_LSQR_TILED", raising=False)
+    assert abs(ht[0] - np.linalg.norm(b.ravel())) < 1e-6 * ht[0]
+    if niter == 0:
+        assert np.all(xt == 0) and np.all(xp == 0)
+    else:
+        assert rel2(xt, xp) < 1e-6
+    assert np.max(np.abs(ht - hp)) / hp[0] < 1e-6
+
+
 def solver_case(mdcmod, case):
     """Operator, right-hand side, solver arguments and oracle operator of one FUSED_CASES entry."""
     kind, nt, nfmax, ns, nr, nv = case
