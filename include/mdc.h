@@ -224,9 +224,10 @@ mdc_status mdc_profile_read(mdc_op* op, double ms[4], int counts[4]);
 /* Autotuner of the per-frequency product (the batch matrix multiplication of
  * Eq.4).  For column counts 1, 2, 3, 4, 6, 8, 12, ... up to max_cols and both
  * directions it times each kernel family on this op's resident kernel -- the
- * streaming kernels (family 0), the matrix-core kernels with 64-column tiles
- * (family 1) and, for complex64 storage, 32-column tiles (family 2) -- and keeps the
- * fastest per width; later applies of N columns use the entry of the smallest tuned
+ * streaming kernels (family 0) and two matrix-core variants: 64- and 32-column tiles
+ * for complex64 storage, four waves of 64 rows and eight waves of 32 rows per
+ * workgroup for the 16-bit formats (families 1 and 2) -- and keeps the fastest per
+ * width; later applies of N columns use the entry of the smallest tuned
  * width >= N.  With cache_path non-NULL, a JSON line per (arch, format, shape) is
  * read if present (*measured = 0) or appended after measuring (*measured = 1).
  * Synchronises the stream; overwrites the op's workspace.  Without tuning, up to 8
