@@ -8,8 +8,11 @@
 //
 // Forward: a wave owns RW rows at a time; lanes stride along the row with
 // 16-byte non-temporal loads (a group of VEC complex values: two in complex64,
-// four in a 16-bit format), the column block of X_f sits in LDS and is reused
-// by the RW rows; a butterfly reduction across the wave closes each row.
+// four in a 16-bit format), the column block of X_f sits in LDS column-major
+// (each lane reads its VEC values of a column as 16-byte pieces, consecutive
+// lanes on consecutive pieces) and is reused by the RW rows; a butterfly
+// reduction across the wave closes each row.  Rows in flight are held as the
+// stored words and widened where they are consumed.
 // Adjoint: a workgroup owns 64*VEC consecutive columns of K_f for all rows
 // (column-block ownership), its four waves split the rows, Y_f sits in LDS and
 // is read as a broadcast, and the four partial sums are added in a fixed
@@ -31,20 +34,29 @@ typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ vf4 ldnt_f4(const void* p) { return __builtin_nontemporal_load(static_cast<const vf4*>(p)); }
 __device__ __forceinline__ vu4 ldnt_u4(const void* p) { return __builtin_nontemporal_load(static_cast<const vu4*>(p)); }
 
-// Kernel formats: VEC complex values per 16-byte group (32 bytes for hi + lo).
+// Kernel formats: VEC complex values per 16-byte group (32 bytes for hi + lo).  Loads keep the
+// stored words (Raw: 16 or 32 bytes per group, so rows in flight cost no more registers than
+// their bytes); unpack widens them to FP32 where they are consumed.
+struct Raw2 {
+  vu4 h, l;
+};
 template <int FMT> struct KF;
 template <> struct KF<MDC_FP32> {
   static constexpr int VEC = 2, GROUP_BYTES = 16;
-  __device__ static void load(const char* g, float2 (&k)[2]) {
-    const vf4 v = ldnt_f4(g);
+  using Raw = vf4;
+  __device__ static Raw load(const char* g) { return ldnt_f4(g); }
+  __device__ static Raw zero() { return vf4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static void unpack(const Raw& v, float2 (&k)[2]) {
     k[0] = make_float2(v.x, v.y);
     k[1] = make_float2(v.z, v.w);
   }
 };
 template <> struct KF<MDC_FP16S> {
   static constexpr int VEC = 4, GROUP_BYTES = 16;
-  __device__ static void load(const char* g, float2 (&k)[4]) {
-    const vu4 v = ldnt_u4(g);
+  using Raw = vu4;
+  __device__ static Raw load(const char* g) { return ldnt_u4(g); }
+  __device__ static Raw zero() { return vu4{0u, 0u, 0u, 0u}; }
+  __device__ static void unpack(const Raw& v, float2 (&k)[4]) {
     const unsigned int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) k[j] = make_float2(f16_bits_to_f(w[j] & 0xFFFFu), f16_bits_to_f(w[j] >> 16));
@@ -52,8 +64,10 @@ template <> struct KF<MDC_FP16S> {
 };
 template <> struct KF<MDC_BF16> {
   static constexpr int VEC = 4, GROUP_BYTES = 16;
-  __device__ static void load(const char* g, float2 (&k)[4]) {
-    const vu4 v = ldnt_u4(g);
+  using Raw = vu4;
+  __device__ static Raw load(const char* g) { return ldnt_u4(g); }
+  __device__ static Raw zero() { return vu4{0u, 0u, 0u, 0u}; }
+  __device__ static void unpack(const Raw& v, float2 (&k)[4]) {
     const unsigned int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) k[j] = make_float2(__uint_as_float(w[j] << 16), __uint_as_float(w[j] & 0xFFFF0000u));
@@ -61,9 +75,11 @@ template <> struct KF<MDC_BF16> {
 };
 template <> struct KF<MDC_BF16X2> {
   static constexpr int VEC = 4, GROUP_BYTES = 32;
-  __device__ static void load(const char* g, float2 (&k)[4]) {
-    const vu4 h = ldnt_u4(g), l = ldnt_u4(g + 16);
-    const unsigned int wh[4] = {h.x, h.y, h.z, h.w}, wl[4] = {l.x, l.y, l.z, l.w};
+  using Raw = Raw2;
+  __device__ static Raw load(const char* g) { return Raw2{ldnt_u4(g), ldnt_u4(g + 16)}; }
+  __device__ static Raw zero() { return Raw2{vu4{0u, 0u, 0u, 0u}, vu4{0u, 0u, 0u, 0u}}; }
+  __device__ static void unpack(const Raw& v, float2 (&k)[4]) {
+    const unsigned int wh[4] = {v.h.x, v.h.y, v.h.z, v.h.w}, wl[4] = {v.l.x, v.l.y, v.l.z, v.l.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       k[j] = make_float2(__uint_as_float(wh[j] << 16) + __uint_as_float(wl[j] << 16),
@@ -91,7 +107,11 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restri
                                                             int groups_per_block, int rc) {
   using F = KF<FMT>;
   constexpr int VEC = F::VEC;
-  extern __shared__ float2 xs[];  // [rc][NC]
+  // chunk of X_f column-major, column c at c * xst: a lane reads its VEC reduction values of a
+  // column as 16-byte pieces, consecutive lanes on consecutive pieces (no bank conflicts); the
+  // stride rc + 2 keeps columns 16-byte aligned and spreads the staging writes over the banks
+  extern __shared__ __attribute__((aligned(16))) float2 xs[];  // [NC][rc + 2]
+  const int xst = rc + 2;
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -119,34 +139,38 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restri
         __syncthreads();
         for (int e = threadIdx.x; e < rlen * NC; e += kThreads) {
           const int rr = e / NC, c = e - (e / NC) * NC;
-          xs[e] = (r0 + rr < nr) ? Xf[(size_t)(r0 + rr) * ldc + col0 + c] : make_float2(0.f, 0.f);
+          xs[c * xst + rr] = (r0 + rr < nr) ? Xf[(size_t)(r0 + rr) * ldc + col0 + c] : make_float2(0.f, 0.f);
         }
         __syncthreads();
       }
       const int npos = rlen / VEC;
       for (int p = lane; p < npos; p += 64) {
-        float2 kv[RW][VEC];
+        typename F::Raw kr[RW];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
           const int s = sbase + i;
-          if (s < ns) {
-            F::load(Kf + (size_t)s * rowb + (size_t)(r0 / VEC + p) * F::GROUP_BYTES, kv[i]);
-          } else {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) kv[i][j] = make_float2(0.f, 0.f);
-          }
+          kr[i] = s < ns ? F::load(Kf + (size_t)s * rowb + (size_t)(r0 / VEC + p) * F::GROUP_BYTES) : F::zero();
         }
+        float2 xv[NC][VEC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int j = 0; j < VEC; ++j) {
-            const float2 x = xs[(VEC * p + j) * NC + c];
-#pragma unroll
-            for (int i = 0; i < RW; ++i) {
-              acc[i][c][0] += kv[i][j].x * x.x - kv[i][j].y * x.y;
-              acc[i][c][1] += kv[i][j].x * x.y + kv[i][j].y * x.x;
-            }
+          for (int j = 0; j < VEC; j += 2) {
+            const float4 t = *reinterpret_cast<const float4*>(&xs[c * xst + VEC * p + j]);
+            xv[c][j] = make_float2(t.x, t.y);
+            xv[c][j + 1] = make_float2(t.z, t.w);
           }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+          float2 kv[VEC];
+          F::unpack(kr[i], kv);
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+              acc[i][c][0] += kv[j].x * xv[c][j].x - kv[j].y * xv[c][j].y;
+              acc[i][c][1] += kv[j].x * xv[c][j].y + kv[j].y * xv[c][j].x;
+            }
         }
       }
     }
@@ -199,28 +223,25 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restri
     __syncthreads();
     // wave w takes rows w*UR .. w*UR+UR-1, then every kWaves*UR rows
     for (int sb = wave * UR; sb < slen; sb += kWaves * UR) {
-      float2 kv[UR][VEC];
+      typename F::Raw kr[UR];
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
         const int ss = sb + u;
-        if (pok && ss < slen) {
-          F::load(Kf + (size_t)(s0 + ss) * rowb + (size_t)p * F::GROUP_BYTES, kv[u]);
-        } else {
-#pragma unroll
-          for (int j = 0; j < VEC; ++j) kv[u][j] = make_float2(0.f, 0.f);
-        }
+        kr[u] = (pok && ss < slen) ? F::load(Kf + (size_t)(s0 + ss) * rowb + (size_t)p * F::GROUP_BYTES) : F::zero();
       }
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
-        const int ss = min(sb + u, slen - 1);  // rows past the end carry kv = 0
+        const int ss = min(sb + u, slen - 1);  // rows past the end carry k = 0
+        float2 kv[VEC];
+        F::unpack(kr[u], kv);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const float2 y = ys[ss * NC + c];
 #pragma unroll
           for (int h = 0; h < VEC; ++h) {
             // conj(k) * y = (kr yr + ki yi) + i (kr yi - ki yr)
-            acc[h][c][0] += kv[u][h].x * y.x + kv[u][h].y * y.y;
-            acc[h][c][1] += kv[u][h].x * y.y - kv[u][h].y * y.x;
+            acc[h][c][0] += kv[h].x * y.x + kv[h].y * y.y;
+            acc[h][c][1] += kv[h].x * y.y - kv[h].y * y.x;
           }
         }
       }
@@ -266,7 +287,7 @@ mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int
     int gpb = (int)((long)ngroups * d.nfmax / 4096);
     gpb = gpb < 1 ? 1 : (gpb > 8 ? 8 : gpb);
     const int nblk = (ngroups + gpb - 1) / gpb;
-    const size_t lds = (size_t)rc * NC * sizeof(float2);
+    const size_t lds = (size_t)(rc + 2) * NC * sizeof(float2);
     hipLaunchKernelGGL((gemv_fwd_kernel<FMT, NC, RW>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
                        out, d.ns, d.nr, ldk, ldc, col0, gpb, rc);
     return check_launch("gemv_fwd_kernel");
