@@ -10,9 +10,11 @@
 // 16-byte non-temporal loads (a group of VEC complex values: two in complex64,
 // four in a 16-bit format), the column block of X_f sits in LDS column-major
 // (each lane reads its VEC values of a column as 16-byte pieces, consecutive
-// lanes on consecutive pieces) and is reused by the RW rows; a butterfly
-// reduction across the wave closes each row.  Rows in flight are held as the
-// stored words and widened where they are consumed.
+// lanes on consecutive pieces) and is reused by the RW rows; the wave's partial
+// sums of all its rows and columns are closed together by recursive halving
+// (n values in n - 1 exchanges).  Rows in flight are held as the stored words
+// and widened where they are consumed; wide column groups load several
+// reduction positions per lane before consuming any.
 // Adjoint: a workgroup owns 64*VEC consecutive columns of K_f for all rows
 // (column-block ownership), its four waves split the rows, Y_f sits in LDS and
 // is read as a broadcast, and the four partial sums are added in a fixed
@@ -93,14 +95,37 @@ __device__ __forceinline__ float out_scale(const float* fscale, int f) {
   else return 1.0f;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
+// Sums each of NP values across the wave by recursive halving: at the exchange with offset O a
+// lane keeps half of the values it holds (the upper half where bit O of the lane is set) and adds
+// its partner's copy of that half, so NP values take NP - 1 exchanges instead of 6 NP.  Once the
+// values are down to one per lane the remaining offsets finish a plain butterfly.  On return v[0]
+// holds the sum of value lane >> (6 - log2 NP), the same on every lane of a group of 64 / NP.
+template <int M, int O>
+struct WaveHalve {
+  template <int NP>
+  __device__ static __forceinline__ void run(float (&v)[NP], int lane) {
+    if constexpr (M > 1) {
+      const bool hi = (lane & O) != 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+      for (int k = 0; k < M / 2; ++k) {
+        const float send = hi ? v[k] : v[k + M / 2];
+        const float keep = hi ? v[k + M / 2] : v[k];
+        v[k] = keep + __shfl_xor(send, O, 64);
+      }
+      WaveHalve<M / 2, O / 2>::run(v, lane);
+    } else if constexpr (O > 0) {
+      v[0] += __shfl_xor(v[0], O, 64);
+      WaveHalve<1, O / 2>::run(v, lane);
+    }
+  }
+};
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+constexpr int log2_exact(int n) { return n <= 1 ? 0 : 1 + log2_exact(n / 2); }
 
 // ---------------------------------------------------------------- forward ---
-template <int FMT, int NC, int RW>
+// UP reduction positions per lane are loaded (UP x RW groups of K in flight) before any is consumed.
+template <int FMT, int NC, int RW, int UP>
 __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restrict__ K, const float* __restrict__ fscale,
                                                             const float2* __restrict__ X, float2* __restrict__ Y,
                                                             int ns, int nr, int ldk, int ldc, int col0,
@@ -144,45 +169,87 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restri
         __syncthreads();
       }
       const int npos = rlen / VEC;
-      for (int p = lane; p < npos; p += 64) {
-        typename F::Raw kr[RW];
+      for (int p0 = lane; p0 < npos; p0 += 64 * UP) {
+        typename F::Raw kr[UP][RW];
 #pragma unroll
-        for (int i = 0; i < RW; ++i) {
-          const int s = sbase + i;
-          kr[i] = s < ns ? F::load(Kf + (size_t)s * rowb + (size_t)(r0 / VEC + p) * F::GROUP_BYTES) : F::zero();
-        }
-        float2 xv[NC][VEC];
+        for (int u = 0; u < UP; ++u)
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int j = 0; j < VEC; j += 2) {
-            const float4 t = *reinterpret_cast<const float4*>(&xs[c * xst + VEC * p + j]);
-            xv[c][j] = make_float2(t.x, t.y);
-            xv[c][j + 1] = make_float2(t.z, t.w);
+          for (int i = 0; i < RW; ++i) {
+            const int s = sbase + i, p = p0 + 64 * u;
+            kr[u][i] = (s < ns && (UP == 1 || p < npos))
+                           ? F::load(Kf + (size_t)s * rowb + (size_t)(r0 / VEC + p) * F::GROUP_BYTES)
+                           : F::zero();
           }
 #pragma unroll
-        for (int i = 0; i < RW; ++i) {
-          float2 kv[VEC];
-          F::unpack(kr[i], kv);
+        for (int u = 0; u < UP; ++u) {
+          const int p = p0 + 64 * u;
+          if (UP > 1 && p >= npos) continue;
+          if constexpr (UP == 1) {  // all columns' X values held, rows widened one at a time
+            float2 xv[NC][VEC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-              acc[i][c][0] += kv[j].x * xv[c][j].x - kv[j].y * xv[c][j].y;
-              acc[i][c][1] += kv[j].x * xv[c][j].y + kv[j].y * xv[c][j].x;
+              for (int j = 0; j < VEC; j += 2) {
+                const float4 t = *reinterpret_cast<const float4*>(&xs[c * xst + VEC * p + j]);
+                xv[c][j] = make_float2(t.x, t.y);
+                xv[c][j + 1] = make_float2(t.z, t.w);
+              }
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+              float2 kv[VEC];
+              F::unpack(kr[u][i], kv);
+#pragma unroll
+              for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                  acc[i][c][0] += kv[j].x * xv[c][j].x - kv[j].y * xv[c][j].y;
+                  acc[i][c][1] += kv[j].x * xv[c][j].y + kv[j].y * xv[c][j].x;
+                }
             }
+          } else {  // all rows widened, X read one column at a time
+            float2 kv[RW][VEC];
+#pragma unroll
+            for (int i = 0; i < RW; ++i) F::unpack(kr[u][i], kv[i]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              float2 xv[VEC];
+#pragma unroll
+              for (int j = 0; j < VEC; j += 2) {
+                const float4 t = *reinterpret_cast<const float4*>(&xs[c * xst + VEC * p + j]);
+                xv[j] = make_float2(t.x, t.y);
+                xv[j + 1] = make_float2(t.z, t.w);
+              }
+#pragma unroll
+              for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                  acc[i][c][0] += kv[i][j].x * xv[j].x - kv[i][j].y * xv[j].y;
+                  acc[i][c][1] += kv[i][j].x * xv[j].y + kv[i][j].y * xv[j].x;
+                }
+            }
+          }
         }
       }
     }
+    // value (i * NC + c) * 2 + z of every lane summed across the wave; one lane per value stores it
+    constexpr int NV = RW * NC * 2, NP = pow2_at_least(NV), SH = 6 - log2_exact(NP);
+    float v[NP];
 #pragma unroll
     for (int i = 0; i < RW; ++i)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const float re = wave_sum(acc[i][c][0]);
-        const float im = wave_sum(acc[i][c][1]);
-        const int s = sbase + i;
-        if (lane == 0 && s < ns) Yf[(size_t)s * ldc + col0 + c] = make_float2(re * osc, im * osc);
+        v[(i * NC + c) * 2] = acc[i][c][0];
+        v[(i * NC + c) * 2 + 1] = acc[i][c][1];
       }
+#pragma unroll
+    for (int k = NV; k < NP; ++k) v[k] = 0.f;
+    WaveHalve<NP, 32>::run(v, lane);
+    const int idx = lane >> SH;
+    if ((lane & ((1 << SH) - 1)) == 0 && idx < NV) {
+      const int ic = idx >> 1, i = ic / NC, c = ic - (ic / NC) * NC;
+      const int s = sbase + i;
+      if (s < ns) reinterpret_cast<float*>(Yf)[((size_t)s * ldc + col0 + c) * 2 + (idx & 1)] = v[0] * osc;
+    }
   }
 }
 
@@ -280,15 +347,22 @@ mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int
                       float2* out, int ldc, int col0, hipStream_t st) {
   constexpr int VEC = KF<FMT>::VEC;
   if (!adjoint) {
-    constexpr int RW = (NC * VEC >= 16) ? 2 : 4;
-    const int rc = (4096 / NC) & ~3;  // chunk of the reduction held in LDS, a multiple of 4
+    // rows per wave: 4 while a row's products fit (NC * VEC <= 8), else 2 with UP positions per lane
+    // in flight (as many as one chunk spans, at most 128 bytes of K per lane)
+    constexpr int RW = (NC * VEC <= 8) ? 4 : 2;
+    // chunk of the reduction held in LDS, a multiple of 4 (equal chunks sized to the reduction, which
+    // raise the occupancy, measured 0.5-6% slower at 1, 2 and 8 columns on the 40 x 40 grid)
+    constexpr int RC = (4096 / NC) & ~3;
+    constexpr int UPC = RC / VEC / 64, UPB = 128 / (RW * KF<FMT>::GROUP_BYTES);
+    constexpr int UP = (NC * VEC <= 8) ? 1 : (UPC < 1 ? 1 : (UPC < UPB ? UPC : UPB));
+    const int rc = RC;
     const int rows_per_group = kWaves * RW;
     const int ngroups = (d.ns + rows_per_group - 1) / rows_per_group;
     int gpb = (int)((long)ngroups * d.nfmax / 4096);
     gpb = gpb < 1 ? 1 : (gpb > 8 ? 8 : gpb);
     const int nblk = (ngroups + gpb - 1) / gpb;
     const size_t lds = (size_t)(rc + 2) * NC * sizeof(float2);
-    hipLaunchKernelGGL((gemv_fwd_kernel<FMT, NC, RW>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
+    hipLaunchKernelGGL((gemv_fwd_kernel<FMT, NC, RW, UP>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
                        out, d.ns, d.nr, ldk, ldc, col0, gpb, rc);
     return check_launch("gemv_fwd_kernel");
   }
