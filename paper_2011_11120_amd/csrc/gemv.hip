@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restri
                                                             int ns, int nr, int ldk, int ldc, int col0, int rcy) {
   using F = KF<FMT>;
   constexpr int VEC = F::VEC;
-  extern __shared__ float2 sh[];  // ys[rcy][NC], then partials [kWaves][VEC*NC*2][64]
+  extern __shared__ float2 sh[];  // ys[rcy][NC], then partials of two waves [2][VEC*NC*2][64]
   float2* ys = sh;
   const int f = blockIdx.y;
   const int lane = threadIdx.x & 63;
@@ -314,16 +314,38 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restri
       }
     }
   }
-  // fixed-order reduction of the four waves' partials
-  __syncthreads();
+  // fixed-order reduction of the four waves' partials, (p0 + p1) + (p2 + p3), in two rounds so that
+  // LDS holds two waves' partials at a time (at 16-bit widths above 4 the four would take 40-64 KB
+  // and halve the workgroups per CU)
   float* part = reinterpret_cast<float*>(sh);
   constexpr int NV = VEC * NC * 2;
+  __syncthreads();
+  if (wave & 1) {
 #pragma unroll
-  for (int h = 0; h < VEC; ++h)
+    for (int h = 0; h < VEC; ++h)
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int z = 0; z < 2; ++z) part[(wave * NV + (h * NC + c) * 2 + z) * 64 + lane] = acc[h][c][z];
+        for (int z = 0; z < 2; ++z) part[((wave >> 1) * NV + (h * NC + c) * 2 + z) * 64 + lane] = acc[h][c][z];
+  }
+  __syncthreads();
+  if (!(wave & 1)) {  // wave 0: p0 + p1, wave 2: p2 + p3
+#pragma unroll
+    for (int h = 0; h < VEC; ++h)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[h][c][z] += part[((wave >> 1) * NV + (h * NC + c) * 2 + z) * 64 + lane];
+  }
+  __syncthreads();
+  if (wave == 2) {
+#pragma unroll
+    for (int h = 0; h < VEC; ++h)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) part[((h * NC + c) * 2 + z) * 64 + lane] = acc[h][c][z];
+  }
   __syncthreads();
   if (wave == 0 && pok) {
     const float osc = out_scale<FMT>(fscale, f);
@@ -331,13 +353,10 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restri
     for (int h = 0; h < VEC; ++h)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        float v[2];
-#pragma unroll
-        for (int z = 0; z < 2; ++z) {
-          const int k = ((h * NC + c) * 2 + z) * 64 + lane;
-          v[z] = ((part[k] + part[NV * 64 + k]) + (part[2 * NV * 64 + k] + part[3 * NV * 64 + k])) * osc;
-        }
-        if (VEC * p + h < nr) Xf[(size_t)(VEC * p + h) * ldc + col0 + c] = make_float2(v[0], v[1]);
+        const int k = ((h * NC + c) * 2) * 64 + lane;
+        const float re = (acc[h][c][0] + part[k]) * osc;
+        const float im = (acc[h][c][1] + part[k + 64]) * osc;
+        if (VEC * p + h < nr) Xf[(size_t)(VEC * p + h) * ldc + col0 + c] = make_float2(re, im);
       }
   }
 }
@@ -371,7 +390,7 @@ mdc_status gemv_group(const mdc_desc& d, const char* K, const float* fscale, int
   constexpr int UR = (NC * VEC >= 16) ? 4 : (NC * VEC <= 4 ? 16 : 8);
   const int rcy = 4096 / NC;
   const size_t lds_y = (size_t)rcy * NC * sizeof(float2);
-  const size_t lds_p = (size_t)kWaves * VEC * NC * 2 * 64 * sizeof(float);
+  const size_t lds_p = (size_t)2 * VEC * NC * 2 * 64 * sizeof(float);  // two waves' partials
   const size_t lds = lds_y > lds_p ? lds_y : lds_p;
   const int nblk = ((d.nr + VEC - 1) / VEC + 63) / 64;
   hipLaunchKernelGGL((gemv_adj_kernel<FMT, NC, UR>), dim3(nblk, d.nfmax), dim3(kThreads), lds, st, K, fscale, in,
