@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kStage = 8;  // loads in flight per thread when a spectra chunk is staged in LDS
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
@@ -162,9 +163,24 @@ __global__ __launch_bounds__(kThreads) void gemv_fwd_kernel(const char* __restri
       const int rlen = min(rc, ldk - r0);  // a multiple of 4: ldk and rc are
       if (nchunks > 1 || g == 0) {
         __syncthreads();
-        for (int e = threadIdx.x; e < rlen * NC; e += kThreads) {
-          const int rr = e / NC, c = e - (e / NC) * NC;
-          xs[c * xst + rr] = (r0 + rr < nr) ? Xf[(size_t)(r0 + rr) * ldc + col0 + c] : make_float2(0.f, 0.f);
+        // kStage loads per thread issued before their stores: one round trip per kStage elements.
+        // The loads are unconditional (an element past the chunk or past nr reads X_f[0][col0] and is
+        // replaced by zero), so none of them waits for the others.
+        const int ne = rlen * NC;
+        for (int e0 = threadIdx.x; e0 < ne; e0 += kThreads * kStage) {
+          float2 t[kStage];
+#pragma unroll
+          for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * kThreads, rr = e / NC, c = e - (e / NC) * NC;
+            const bool ok = e < ne && r0 + rr < nr;
+            const float2 v = Xf[ok ? (size_t)(r0 + rr) * ldc + col0 + c : (size_t)col0];
+            t[u] = ok ? v : make_float2(0.f, 0.f);
+          }
+#pragma unroll
+          for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * kThreads, rr = e / NC, c = e - (e / NC) * NC;
+            if (e < ne) xs[c * xst + rr] = t[u];
+          }
         }
         __syncthreads();
       }
@@ -283,9 +299,20 @@ __global__ __launch_bounds__(kThreads) void gemv_adj_kernel(const char* __restri
   for (int s0 = 0; s0 < ns; s0 += rcy) {
     const int slen = min(rcy, ns - s0);
     __syncthreads();
-    for (int e = threadIdx.x; e < slen * NC; e += kThreads) {
-      const int ss = e / NC, c = e - (e / NC) * NC;
-      ys[e] = Yf[(size_t)(s0 + ss) * ldc + col0 + c];
+    const int ne = slen * NC;
+    // kStage unconditional loads per thread before their stores (past the chunk: Y_f[s0][col0], unused)
+    for (int e0 = threadIdx.x; e0 < ne; e0 += kThreads * kStage) {
+      float2 t[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = e0 + u * kThreads, ss = e / NC, c = e - (e / NC) * NC;
+        t[u] = Yf[e < ne ? (size_t)(s0 + ss) * ldc + col0 + c : (size_t)s0 * ldc + col0];
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < ne) ys[e] = t[u];
+      }
     }
     __syncthreads();
     // wave w takes rows w*UR .. w*UR+UR-1, then every kWaves*UR rows
