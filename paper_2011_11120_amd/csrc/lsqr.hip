@@ -80,7 +80,15 @@ __global__ __launch_bounds__(kThreads) void finish_norm(const double* __restrict
                                                         int nparts) {
   __shared__ double sh[kThreads / 64];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += part[i];
+  // eight loads in flight per thread (clamped, unconditional), added in the order of a plain strided loop
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += kThreads * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[i0 + u * kThreads < nparts ? i0 + u * kThreads : 0];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * kThreads < nparts) acc += v[u];
+  }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(t);
