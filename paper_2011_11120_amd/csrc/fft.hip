@@ -142,10 +142,23 @@ __device__ __forceinline__ void fft_lds(float2* lds, const float2* tws, int tid)
   for (; Ns < M; Ns *= 8) stockham_pass<M, CB, DIR, 8, NTH>(lds, tws, tid, Ns);
 }
 
+// The 2M-entry twiddle table copied to LDS in two halves: load() issues this thread's entries
+// (clamped addresses, unconditional) before the tile's own loads, store() writes them to LDS once
+// the tile's loads are in flight, so the table's round trip overlaps the tile's.
 template <int M, int NTH>
-__device__ __forceinline__ void stage_twiddles(float2* tws, const float2* __restrict__ tw, int tid) {
-  for (int k = tid; k < 2 * M; k += NTH) tws[k] = tw[k];
-}
+struct TwiddleStage {
+  static constexpr int N = (2 * M + NTH - 1) / NTH;
+  float2 t[N];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int tid) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = tw[min(tid + i * NTH, 2 * M - 1)];
+  }
+  __device__ __forceinline__ void store(float2* tws, int tid) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (tid + i * NTH < 2 * M) tws[tid + i * NTH] = t[i];
+  }
+};
 
 // Workgroup number with neighbouring trace groups on the same XCD (hardware deals
 // workgroups round-robin over the 8 XCDs): two neighbours share 128-byte lines of
@@ -181,7 +194,8 @@ __global__ __launch_bounds__(NTH) void rfft_trunc_kernel(
   const int Q = n * nv;
   const int tid = threadIdx.x;
   const int q0 = xcd_block() * CB;
-  stage_twiddles<M, NTH>(tws, tw, tid);
+  TwiddleStage<M, NTH> twl;
+  twl.load(tw, tid);
   const float ds = dscale != nullptr ? (float)*dscale : 1.0f;
 
   if constexpr (VEC) {
@@ -247,6 +261,7 @@ __global__ __launch_bounds__(NTH) void rfft_trunc_kernel(
       lds[m * CB + col] = make_float2(a, b);
     }
   }
+  twl.store(tws, tid);
   __syncthreads();
   fft_lds<M, CB, -1, NTH>(lds, tws, tid);
 
@@ -304,13 +319,13 @@ __global__ __launch_bounds__(NTH) void irfft_pad_kernel(
   const int Q = n * nv;
   const int tid = threadIdx.x;
   const int q0 = xcd_block() * CB;
-  stage_twiddles<M, NTH>(tws, tw, tid);
+  TwiddleStage<M, NTH> twl;
+  twl.load(tw, tid);
   const float iscale = ident_dscale != nullptr ? iscale0 * (float)*ident_dscale : iscale0;
   // fused recurrence: out += coef * out_old, coefficient formed in FP64 as the separate pass does
   const bool acc = acc_c1 != nullptr;
   const float coef = acc ? (float)((double)acc_sgn * *acc_c1 * (acc_c2 != nullptr ? *acc_c2 : 1.0)) : 0.f;
   double ssq = 0.0;
-  __syncthreads();
 
   // Bins k and M - k of the trace pair (q, q + 1); every load of the tile is issued before
   // any is consumed, from clamped addresses (unpredicated), invalid bins zeroed afterwards.
@@ -345,6 +360,8 @@ __global__ __launch_bounds__(NTH) void irfft_pad_kernel(
   }
   // the middle bin M/2 is its own mirror: every thread loads it for trace pair min(tid, CP - 1)
   bin2(M / 2, q0 + 2 * min(tid, CP - 1), gm[0], gm[1]);
+  twl.store(tws, tid);
+  __syncthreads();
   auto split = [&](int k, int p, float2 (&a)[2], float2 (&b)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
