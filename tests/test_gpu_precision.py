@@ -83,6 +83,27 @@ def test_streaming_widths_match_oracle(mdcmod, monkeypatch, prec, nv):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp16s"])
+@pytest.mark.parametrize("nv", [5, 8])
+def test_streaming_chunks_match_oracle(mdcmod, monkeypatch, prec, nv):
+    """Wide column groups over reductions longer than one LDS chunk: the forward stages X in chunks
+    of 4096 / nv positions (two or three here, the last one short) with several positions per lane
+    in flight, the adjoint stages Y in chunks of 4096 / nv rows (two here)."""
+    monkeypatch.setenv("MDC_PRODUCT", "gemv")
+    nt, nfmax, ns, nr = 64, 8, 900, 1100
+    K = synth.random_complex_kernel(nfmax, ns, nr, seed=11 * nv)
+    op = mdcmod.MdcOp(nt, nfmax, ns, nr, max_cols=nv, prec=prec)
+    op.set_kernel(dev(K, torch.complex64))
+    x = synth.gaussian((nt, nr, nv), seed=12)
+    y = synth.gaussian((nt, ns, nv), seed=13)
+    ef = relmax(host(op.forward(dev(x))), om.mdc_forward(K, x))
+    ea = relmax(host(op.adjoint(dev(y))), om.mdc_adjoint(K, y))
+    tol = 1e-5 if prec == "fp32" else TOL[prec]
+    print(f"chunked streaming {prec} nv={nv}: forward {ef:.2e} adjoint {ea:.2e}", flush=True)
+    assert ef < tol and ea < tol
+    op.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("bf16x2", 1e-5), ("fp16s", 1e-5), ("bf16", 1e-5), ("fp16", 2.0 ** -11)])
 def test_formats_dot_product(mdcmod, prec, tol):
     """The forward and adjoint read the same stored kernel, so the pair stays adjoint; with FP16
