@@ -101,22 +101,23 @@ float time_family(mdc_op* op, int fam, int adjoint, int ncols, hipStream_t st) {
   float2* in = adjoint ? op->specS : op->specR;
   float2* out = adjoint ? op->specR : op->specS;
   hipEvent_t a = nullptr, b = nullptr;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  float best = 3.0e38f;
-  if (run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit) == MDC_OK) {  // warm-up
+  float best = 3.0e38f;  // a family that cannot be timed is never chosen
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+      run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit) == MDC_OK) {  // warm-up
     for (int rep = 0; rep < 3; ++rep) {
-      hipEventRecord(a, st);
-      run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit);
-      hipEventRecord(b, st);
-      hipEventSynchronize(b);
       float ms = 0.f;
-      hipEventElapsedTime(&ms, a, b);
+      if (hipEventRecord(a, st) != hipSuccess ||
+          run_family(op, fam, adjoint, in, out, ncols, st, op->d, op->bsplit) != MDC_OK ||
+          hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+          hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        best = 3.0e38f;
+        break;
+      }
       best = ms < best ? ms : best;
     }
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
   return best;
 }
 
@@ -180,15 +181,20 @@ struct Stage {
   Stage(mdc_op* o, int s, hipStream_t stream) : op(o), stage(s), st(stream) {
     if (op->prof) {
       a = take_event(op);
-      if (a) hipEventRecord(a, st);
+      if (a && hipEventRecord(a, st) != hipSuccess) {  // unrecorded: this stage goes untimed
+        op->pool.push_back(a);
+        a = nullptr;
+      }
     }
   }
   ~Stage() {
     if (op->prof && a) {
       hipEvent_t b = take_event(op);
-      if (b) {
-        hipEventRecord(b, st);
+      if (b && hipEventRecord(b, st) == hipSuccess) {
         op->evs.push_back({stage, a, b});
+      } else {
+        op->pool.push_back(a);
+        if (b) op->pool.push_back(b);
       }
     }
   }
@@ -972,16 +978,16 @@ mdc_status cgls_solve(mdc_op* op, const lsqr_desc* ld, const float* b, float* x,
 
 mdc_status mdc_destroy(mdc_op* op) {
   if (!op) return MDC_OK;
-  if (op->lsqr_exec) hipGraphExecDestroy(op->lsqr_exec);
+  if (op->lsqr_exec) (void)hipGraphExecDestroy(op->lsqr_exec);
   if (op->cap_stream) {
-    hipStreamSynchronize(op->cap_stream);
-    hipStreamDestroy(op->cap_stream);
+    (void)hipStreamSynchronize(op->cap_stream);
+    (void)hipStreamDestroy(op->cap_stream);
   }
   for (auto& e : op->evs) {
-    hipEventDestroy(e.a);
-    hipEventDestroy(e.b);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
-  for (auto e : op->pool) hipEventDestroy(e);
+  for (auto e : op->pool) (void)hipEventDestroy(e);
   delete op;
   return MDC_OK;
 }

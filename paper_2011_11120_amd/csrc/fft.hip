@@ -503,8 +503,10 @@ mdc_status rfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const F
   const float scale = (float)(1.0 / std::sqrt((double)(2 * M)));
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)rfft_trunc_kernel<M, CB, VEC, CONTIG, NTH>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void*)rfft_trunc_kernel<M, CB, VEC, CONTIG, NTH>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+      return fail(MDC_EDEVICE, "rfft_trunc_kernel: %zu bytes of LDS refused: %s", lds, hipGetErrorString(e));
     attr = true;
   }
   hipLaunchKernelGGL((rfft_trunc_kernel<M, CB, VEC, CONTIG, NTH>), dim3((Q + CB - 1) / CB), dim3(NTH), lds, st, s.in,
@@ -542,8 +544,10 @@ mdc_status irfft_run(const float2* tw, int nfmax, int n, int nv, int ldc, const 
   const float scale = (float)(1.0 / std::sqrt((double)(2 * M)));
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)irfft_pad_kernel<M, CB, VEC, CONTIG, NTH>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void*)irfft_pad_kernel<M, CB, VEC, CONTIG, NTH>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+      return fail(MDC_EDEVICE, "irfft_pad_kernel: %zu bytes of LDS refused: %s", lds, hipGetErrorString(e));
     attr = true;
   }
   hipLaunchKernelGGL((irfft_pad_kernel<M, CB, VEC, CONTIG, NTH>), dim3((Q + CB - 1) / CB), dim3(NTH), lds, st, spec,

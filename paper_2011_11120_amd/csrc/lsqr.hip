@@ -475,7 +475,7 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
   const LsqrGraphKey key{kind, ld.nv, S.rpart != nullptr, tiled, op->tune_gen, forced_family(op), ld.onset, work, x, hist, b};
   if (!op->lsqr_exec || !(op->lsqr_key == key)) {
     if (op->lsqr_exec) {
-      hipGraphExecDestroy(op->lsqr_exec);
+      (void)hipGraphExecDestroy(op->lsqr_exec);
       op->lsqr_exec = nullptr;
     }
     if (!op->cap_stream && hipStreamCreate(&op->cap_stream) != hipSuccess)
@@ -486,12 +486,12 @@ mdc_status lsqr_run(mdc_op* op, const mdc_desc& d, const lsqr_desc& ld, const fl
     const mdc_status cs = iteration(op->cap_stream);
     const hipError_t ce = hipStreamEndCapture(op->cap_stream, &graph);
     if (cs != MDC_OK) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return cs;
     }
     if (ce != hipSuccess || !graph) return fail(MDC_EDEVICE, "hipStreamEndCapture failed");
     const hipError_t ie = hipGraphInstantiate(&op->lsqr_exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) {
       op->lsqr_exec = nullptr;
       return fail(MDC_EDEVICE, "hipGraphInstantiate failed");

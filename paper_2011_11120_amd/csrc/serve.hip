@@ -375,7 +375,7 @@ void advance(std::vector<Request*>& part, bool fwd) {
 }
 
 void drop_graphs(mdc_server* S) {
-  for (auto& kv : S->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second);
   S->graphs.clear();
 }
 
@@ -408,14 +408,14 @@ mdc_status run_step(mdc_server* S, std::vector<Request*>& part, bool fwd) {
         const mdc_status cs = enqueue_step(S, part, fwd, st);
         ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph != nullptr && cs == MDC_OK;
         ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
       }
       if (ok) {
         S->graphs[key] = exec;
         S->captured += 1;
         if (hipGraphLaunch(exec, st) != hipSuccess) s = fail(MDC_EDEVICE, "hipGraphLaunch failed");
       } else {  // capture unavailable: run eagerly from now on (nothing of the capture executed)
-        hipGetLastError();
+        (void)hipGetLastError();  // clear the failed capture's error
         S->graphs_ok = false;
         s = enqueue_step(S, part, fwd, st);
       }
@@ -480,7 +480,7 @@ void release(mdc_server* S, Request* r) {
 }
 
 void worker_main(mdc_server* S) {
-  hipSetDevice(S->device);
+  (void)hipSetDevice(S->device);  // the device serve_create ran on, current there
   const int max_cols = S->op->d.max_cols;
   while (true) {
     std::vector<Request*> part, deferred_now;
@@ -663,10 +663,10 @@ mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t
     if (!(g->sublattice & dd)) continue;
     const mdc_status ls = make_level(S, dd);
     if (ls != MDC_OK) {
-      hipStreamSynchronize(S->stream);
+      (void)hipStreamSynchronize(S->stream);
       for (auto& L : S->lv)
         if (L.op && L.op != op) mdc_destroy(L.op);
-      hipStreamDestroy(S->stream);
+      (void)hipStreamDestroy(S->stream);
       delete S;
       return ls;
     }
@@ -674,7 +674,7 @@ mdc_status serve_create(mdc_op* op, const serve_geometry* g, void* arena, size_t
   if (hipStreamSynchronize(S->stream) != hipSuccess) {
     for (auto& L : S->lv)
       if (L.op && L.op != op) mdc_destroy(L.op);
-    hipStreamDestroy(S->stream);
+    (void)hipStreamDestroy(S->stream);
     delete S;
     return fail(MDC_EDEVICE, "preparing the lattice levels failed");
   }
@@ -824,9 +824,9 @@ mdc_status serve_destroy(mdc_server* S) {
   }
   S->cv.notify_all();
   if (S->worker.joinable()) S->worker.join();
-  hipStreamSynchronize(S->stream);
+  (void)hipStreamSynchronize(S->stream);
   drop_graphs(S);
-  hipStreamDestroy(S->stream);
+  (void)hipStreamDestroy(S->stream);
   for (auto& L : S->lv)
     if (L.op && L.op != S->op) mdc_destroy(L.op);
   for (auto& kv : S->all) delete kv.second;
